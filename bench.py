@@ -1,0 +1,184 @@
+"""Online FISTA throughput on one MI355X: pulses/s on the 64x64 Haar workload.
+
+One step = one whole image: reset of the online state, then for each of the
+P = 128 pulses push_pulse (rows, Haar fold, b and Gram update, L_n) and
+reconstruct(20) (20 fused matvec/shrink/momentum steps).  Echoes are
+synthesised on the device before timing (inputs resident in HBM).
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (per-launch durations from HIP events on the library's stream) and
+the FP64 oracle timed on the host as a reported CPU baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "pulses/sec (Gram update + 20 FISTA iters) at 64×64 scene; % HBM/MFMA peak"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = ROOT / "profiles" / "traffic_haar64.json"
+KERNEL_SOURCES = {"step": "paper_2603_08582_amd/csrc/fista.hip",
+                  "gram": "paper_2603_08582_amd/csrc/gram.hip"}
+
+
+def source_hash(rel: str) -> str:
+    return hashlib.sha256((ROOT / rel).read_bytes()).hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on a different kernel source."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    rec = json.loads(TRAFFIC_FILE.read_text()).get(kernel)
+    if not rec or rec.get("source_sha") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, pulses: int):
+    """The FP64 oracle as it stands, on the first `pulses` pulses."""
+    from oracle import sar
+    from oracle.online_fista import OnlineFistaOracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"), default=1)
+    except Exception:
+        threads = os.cpu_count() or 1
+    d = sar.echoes(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    m = wl.spec.inner_steps
+    t0 = time.perf_counter()
+    for p in range(pulses):
+        o.push_pulse(d[p], p)
+        o.reconstruct(m)
+    dt = time.perf_counter() - t0
+    return {"value": pulses / dt, "unit": "pulses/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {pulses} of {wl.spec.n_pulses} pulses of the same workload "
+                      f"(push + {m} FISTA steps each), numpy complex128, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="haar64")
+    ap.add_argument("--cpu-pulses", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of "
+              "Online FISTA is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_08582_amd import OnlineFista
+    from workload import library_kwargs, make_workload
+
+    wl = make_workload(args.workload)
+    s = wl.spec
+    N, K, P, m = s.n_pixels, s.n_freq, s.n_pulses, s.inner_steps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    g = OnlineFista(device=dev, **library_kwargs(wl))
+    stream = g.stream
+
+    # inputs: echoes synthesised on the device from the seeded scene and noise
+    rho = torch.from_numpy(wl.rho.astype(np.complex64)).to(dev)
+    noise = torch.from_numpy(wl.noise.astype(np.complex64)).to(dev)
+    d = torch.empty((P, K), dtype=torch.complex64, device=dev)
+    for p in range(P):
+        g.echo(p, rho, noise[p], s.snr_db, float(wl.phase_err[p]), out=d[p])
+    torch.cuda.synchronize()
+
+    def step():
+        g.reset()
+        for p in range(P):
+            g.push_pulse(d[p], p)
+            g.reconstruct(m, copy=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+
+    # per-kernel durations: the same steps again with HIP events around every
+    # launch of the Gram update and of the FISTA step (library stream)
+    g.profile(True)
+    for _ in range(args.steps):
+        step()
+    gram_ms, gram_n = g.kernel_time("gram")
+    step_ms, step_n = g.kernel_time("step")
+    g.profile(False)
+    x = g.image()
+    torch.cuda.synchronize()
+    finite = bool(torch.isfinite(torch.view_as_real(x)).all().item())
+
+    gram_avg = gram_ms / max(gram_n, 1)
+    step_avg = step_ms / max(step_n, 1)
+    gram_flops = 4.0 * K * N * (N + 1)          # Hermitian upper triangle, per pulse
+    step_bytes = 4.0 * N * (N + 1)              # upper-triangle complex64 H, per FISTA step
+    rl_gram = {"bound": "mfma", "achieved": gram_flops / (gram_avg * 1e-3) / 1e12,
+               "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic_for("gram"),
+               "kernel": "k_gram_fp32", "avg_ms": gram_avg, "launches": gram_n}
+    rl_step = {"bound": "hbm", "achieved": step_bytes / (step_avg * 1e-3) / 1e9,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step"),
+               "kernel": "k_fista_step", "avg_ms": step_avg, "launches": step_n}
+    for r in (rl_gram, rl_step):
+        r["frac"] = r["achieved"] / r["peak"]
+    dominant, other = (rl_step, rl_gram) if step_ms >= gram_ms else (rl_gram, rl_step)
+
+    out = {
+        "metric": METRIC,
+        "value": P / (ms * 1e-3),
+        "unit": "pulses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: {s.n_side}x{s.n_side} pixels (N={N}), "
+                               f"{s.dictionary}({s.haar_levels}) dictionary, K={K}, "
+                               f"P={P} pulses, m={m} FISTA steps per pulse, one step = one image",
+                   "N": N, "K": K, "pulses": P, "inner_steps": m, "seed": s.seed,
+                   "storage": "packed Hermitian upper tiles 64x64, complex64",
+                   "parallelism": "single GPU"},
+        "fista_iters_per_s": P * m / (ms * 1e-3),
+        "roofline": {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": dominant["kernel"],
+        "roofline_other": other,
+        "roofline_dominant_detail": {"avg_ms": dominant["avg_ms"], "launches": dominant["launches"]},
+        "image_finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * ofista.h -- C ABI of the MI355X (gfx950) Online FISTA library, libofista.so.
+ *
+ * Online FISTA (Flynn, Ivanov, Yazici, "Online Sparse Synthetic Aperture Radar
+ * Imaging") reconstructs a sparse SAR scene pulse by pulse.  For every received
+ * pulse d_s it forms the per-pulse forward operator A_s = F_s W (Section III-A,
+ * eq. for G), folds it into the running sufficient statistics
+ * H += A_s^H A_s and b += A_s^H d_s (Section III-C, the Delta-A / Delta-b and
+ * A_n / b_n equations; the paper's A_n is called H here), picks the step
+ * tau = 1/L_n (Section III-B spectral-norm condition and the incremental bound
+ * of Section III-C), and runs m warm-started FISTA steps (Algorithm 1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Complex values are complex64: two consecutive floats (re, im).
+ * - Pixels form an n_x by n_y grid on the plane z = 0; pixel (iy, ix) sits at
+ *   (x0 + ix*dx, y0 + iy*dy, 0) and has flat index i = iy*n_x + ix; N = n_x*n_y.
+ *   Coefficients use the same flat index (M = N for both dictionaries).
+ * - The kernel of F_s is exp(-i 4 pi f_k R_{s,i} / c0) with R the Euclidean
+ *   distance between platform position s and pixel i and f_k = freq0 + k*dfreq
+ *   (the Section II phase with amplitude 1, on a stepped-frequency grid).
+ *   Range and phase are evaluated in FP64 on the device.
+ * - Device pointers ("d_" prefix) must point to device memory of the device
+ *   that was current at ofista_create; host pointers are plain host memory.
+ * - Every call that takes a ctx enqueues its device work on the stream given
+ *   to ofista_create and returns without waiting, unless stated otherwise.
+ * - A ctx is single-threaded: calls on one ctx must not overlap.
+ * - Errors are returned as ofista_status; nothing throws or aborts across the
+ *   ABI.  After OFISTA_E_HIP the ctx is poisoned and every later call on it
+ *   returns OFISTA_E_STATE (ofista_destroy still works).
+ */
+#ifndef OFISTA_H
+#define OFISTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ofista_status {
+  OFISTA_OK = 0,
+  OFISTA_E_ARG = -1,         /* null pointer, bad size or enum value         */
+  OFISTA_E_RANGE = -2,       /* pulse index outside [0, n_pos)               */
+  OFISTA_E_STATE = -3,       /* call not valid now (e.g. no pulse yet), or
+                                the ctx is poisoned by an earlier HIP error  */
+  OFISTA_E_WORKSPACE = -4,   /* workspace null, misaligned or too small      */
+  OFISTA_E_UNSUPPORTED = -5, /* valid but unsupported combination            */
+  OFISTA_E_HIP = -6          /* a HIP runtime call failed (ctx poisoned)     */
+} ofista_status;
+
+enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1 };
+/* Arithmetic of the Gram update: FP32 MFMA, or BF16 MFMA on a hi+lo split of
+   each operand (three products, FP32 accumulation). */
+enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
+/* L_n rule: RUNNING = rho_{n-1} + sigma_n^2 (rho: Rayleigh quotient of a power
+   vector advanced once per FISTA step on the current H); BOUND = L_{n-1} +
+   sigma_n^2 (the incremental bound of Section III-C taken literally).
+   sigma_n^2 = ||A_s||_2^2 from an FP64 power iteration (at most 200 steps,
+   stop at 1e-13 relative change of the Rayleigh quotient, start 1/sqrt(K)). */
+enum { OFISTA_LIP_RUNNING = 0, OFISTA_LIP_BOUND = 1 };
+/* Momentum across pulses: FISTA = t carried from pulse to pulse (Algorithm 1);
+   RESTART = t = 1 at every reconstruct; ISTA = no momentum (beta = 0). */
+enum { OFISTA_MOMENTUM_FISTA = 0, OFISTA_MOMENTUM_RESTART = 1, OFISTA_MOMENTUM_ISTA = 2 };
+
+typedef struct ofista_config {
+  int32_t n_x, n_y;        /* pixel grid; N = n_x*n_y >= 1                    */
+  double x0, y0, dx, dy;   /* centre of pixel (0,0) and spacing, metres       */
+  int32_t n_pos;           /* platform positions available to push_pulse      */
+  const double *pos_xyz;   /* host, n_pos*3 doubles (x, y, z per position);
+                              copied during ofista_create                     */
+  int32_t n_freq;          /* K >= 1 frequencies per pulse                    */
+  double freq0_hz;         /* f_0                                             */
+  double dfreq_hz;         /* f_{k+1} - f_k                                   */
+  int32_t dict;            /* OFISTA_DICT_*; HAAR2D needs n_x == n_y, both
+                              divisible by 2^haar_levels, and N <= 8192       */
+  int32_t haar_levels;     /* levels of the 2-D Haar dictionary (>= 1)        */
+  double lambda;           /* l1 weight; if lambda_relative != 0 it is the
+                              factor r in lambda = r * max_i |A_1^H d_1|_i,
+                              fixed at the first pulse                       */
+  int32_t lambda_relative;
+  int32_t precision;       /* OFISTA_PREC_*                                    */
+  int32_t lipschitz;       /* OFISTA_LIP_*                                     */
+  int32_t momentum;        /* OFISTA_MOMENTUM_*                                */
+  int32_t record_every;    /* > 0: keep what ofista_backward needs, with a
+                              state checkpoint every record_every pulses     */
+  int32_t max_pulses;      /* pulses that can be recorded (record_every > 0) */
+  int32_t max_iters;       /* inner steps per reconstruct that can be
+                              recorded (record_every > 0)                    */
+} ofista_config;
+
+typedef struct ofista_stats {
+  int64_t n_pulses;        /* pulses pushed since create/reset                */
+  int64_t n_iters;         /* FISTA steps run since create/reset              */
+  double t;                /* momentum scalar t_n                             */
+  double L;                /* current L_n                                     */
+  double tau;              /* 1/L_n                                           */
+  double lambda;           /* l1 weight in use (0 before the first pulse when
+                              relative)                                       */
+  double rho;              /* Rayleigh quotient of the running power vector   */
+  double sigma2;           /* ||A_s||_2^2 of the last pushed pulse            */
+} ofista_stats;
+
+/* Device bytes the workspace must have for cfg (H, b, coefficient and momentum
+   vectors, power vector, matvec partials, one pulse's A_s, tables, and the
+   recording buffers when record_every > 0).  Pure host function, needs no GPU.
+   Returns 0 when cfg is invalid. */
+size_t ofista_workspace_bytes(const ofista_config *cfg);
+
+/* Checks cfg without touching the GPU; OFISTA_OK if ofista_create would
+   accept it (workspace aside). */
+ofista_status ofista_check_config(const ofista_config *cfg);
+
+/* init(scene, geometry, lambda).  Validates cfg, carves the caller-owned
+   workspace (device memory of at least ofista_workspace_bytes(cfg) bytes,
+   256-byte aligned, kept alive by the caller until ofista_destroy), copies the
+   host tables, precomputes ||A_s||_2^2 for every position (it depends only on
+   the geometry) and zeroes the state.  hip_stream is a hipStream_t (NULL =
+   the null stream).  The ctx (host memory) is owned by the library. */
+ofista_status ofista_create(const ofista_config *cfg, void *d_workspace,
+                            size_t workspace_bytes, void *hip_stream,
+                            struct ofista_ctx **out);
+
+/* Zero the online state (H, b, c, t, L, lambda, power vector, pulse count) so
+   that a new image can be formed with the same geometry tables. */
+ofista_status ofista_reset(struct ofista_ctx *ctx);
+
+/* push_pulse(d_s, s): one received pulse.  d_pulse: device, K complex64; s:
+   index of the platform position (0 <= s < n_pos; positions may repeat or be
+   skipped).  The data used is d_s * exp(-i phase_corr).  Enqueues A_s, the H
+   and b updates, lambda at the first pulse, and L_n, tau. */
+ofista_status ofista_push_pulse(struct ofista_ctx *ctx, const void *d_pulse,
+                                int32_t s, double phase_corr);
+
+/* reconstruct(iters): Algorithm 1 with iters inner steps on the current
+   (H_n, b_n), warm-started from c_hat_{n-1} and t_{n-1}.  iters may be 0.
+   d_coef_out: device, N complex64, receives c_hat_n (NULL = not copied).
+   OFISTA_E_STATE before the first pulse. */
+ofista_status ofista_reconstruct(struct ofista_ctx *ctx, int32_t iters,
+                                 void *d_coef_out);
+
+/* Image x = W c_hat (Section III-B, rho ~ H c with the paper's dictionary H).
+   d_img_out: device, N complex64. */
+ofista_status ofista_image(struct ofista_ctx *ctx, void *d_img_out);
+
+/* Host copy of the scalar state.  Synchronises the stream. */
+ofista_status ofista_state(struct ofista_ctx *ctx, ofista_stats *out);
+
+/* Synthetic radar return for position s (the Section II measurement model):
+   d = exp(i phase_err) F_s rho + sigma * noise, sigma^2 = |F_s rho|^2 / K *
+   10^(-snr_db/10).  d_rho: device, N complex64 pixel reflectivities; d_noise:
+   device, K complex64 unit-variance draws, or NULL for a noiseless echo;
+   d_out: device, K complex64.  Uses the ctx's scratch rows (do not overlap
+   with push_pulse on another thread -- ctx calls never overlap anyway). */
+ofista_status ofista_echo(struct ofista_ctx *ctx, int32_t s, const void *d_rho,
+                          const void *d_noise, double snr_db, double phase_err,
+                          void *d_out);
+
+/* Inspection.  ofista_rows: A_s for position s into d_out (K x N complex64,
+   row k contiguous).  ofista_gram: the Hermitian H_n expanded to a dense
+   N x N complex64 matrix (row-major; N <= 16384, else OFISTA_E_UNSUPPORTED).  ofista_vector: which = 0 b, 1 c_hat,
+   2 power vector w (unnormalised), N complex64 each. */
+ofista_status ofista_rows(struct ofista_ctx *ctx, int32_t s, void *d_out);
+ofista_status ofista_gram(struct ofista_ctx *ctx, void *d_out);
+ofista_status ofista_vector(struct ofista_ctx *ctx, int32_t which, void *d_out);
+
+/* Resumable state record (n, t, L, lambda, power vector, c_hat, b, H), so that
+   a run split at any pulse and resumed equals the uninterrupted run.  The
+   buffer is caller-owned device memory of ofista_state_bytes(cfg) bytes. */
+size_t ofista_state_bytes(const ofista_config *cfg);
+ofista_status ofista_export_state(struct ofista_ctx *ctx, void *d_buf);
+ofista_status ofista_import_state(struct ofista_ctx *ctx, const void *d_buf);
+
+/* Per-kernel timing with HIP events on the ctx's stream.  While enabled, every
+   launch of the named kernel class is bracketed by a pair of events.
+   ofista_kernel_time synchronises and returns the summed milliseconds and the
+   launch count since enabling.  kernel: 0 Gram update, 1 FISTA step (matvec +
+   shrink + momentum), 2 rows, 3 correlation, 4 scalars. */
+ofista_status ofista_profile(struct ofista_ctx *ctx, int32_t enable);
+ofista_status ofista_kernel_time(struct ofista_ctx *ctx, int32_t kernel,
+                                 double *total_ms, int64_t *launches);
+
+/* Free the host ctx (the workspace stays the caller's). NULL is ignored. */
+void ofista_destroy(struct ofista_ctx *ctx);
+
+/* Static message for a status; with a ctx, the last detailed message. */
+const char *ofista_error_string(const struct ofista_ctx *ctx, ofista_status st);
+
+/* Layout constants of this build (for tests): tile edge of the packed
+   Hermitian storage. */
+int32_t ofista_tile(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFISTA_H */

@@ -1,0 +1,72 @@
+"""Build libofista.so in-tree with hipcc for gfx950.
+
+    python -m paper_2603_08582_amd.build        (or build() from Python)
+
+Every HIP source is compiled with packed-FP32 instructions disabled
+(-target-feature -packed-fp32-ops) and linked into one shared library next
+to this file.  The oracle's C parts (if any) are built by __graft_entry__.
+"""
+
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+from pathlib import Path
+
+HERE = Path(__file__).resolve().parent
+CSRC = HERE / "csrc"
+INCLUDE = HERE.parent / "include"
+LIB = HERE / "libofista.so"
+BUILD = HERE.parent / "_build" / "ofista"
+
+ARCH = os.environ.get("OFISTA_ARCH", "gfx950")
+SOURCES = ["rows.hip", "gram.hip", "fista.hip", "runtime.cpp"]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and Path(cand).exists():
+            return cand
+    raise RuntimeError("hipcc not found: install ROCm or set HIPCC")
+
+
+def _flags():
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function",
+            "-Wno-unknown-warning-option"]
+
+
+def _compile(src: str) -> Path:
+    BUILD.mkdir(parents=True, exist_ok=True)
+    obj = BUILD / (src + ".o")
+    cmd = [hipcc(), *_flags(), "-c", str(CSRC / src), "-o", str(obj)]
+    if src.endswith(".cpp"):
+        cmd.insert(1, "-x")
+        cmd.insert(2, "hip")
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False) -> Path:
+    with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES))
+    tmp = LIB.with_suffix(".so.tmp")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs),
+           "-o", str(tmp)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}", file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

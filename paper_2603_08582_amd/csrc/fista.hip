@@ -1,0 +1,312 @@
+// One step of Algorithm 1 (Online FISTA, inner loop) as a single launch:
+//   y = H z, g = y - b, u = z - tau g, c = S_{lambda tau}(u),
+//   z' = c + beta (c - c_prev)
+// fused with one power-iteration step on the same pass over H:
+//   y_w = H w, rho parts Re<w, y_w>, w' = y_w / |w|.
+//
+// H is stored as packed upper tiles, so each tile (I, J), I < J, serves two
+// products: y_I += H_IJ z_J (rows) and y_J += H_IJ^H z_I (columns).  This is
+// the memory-bound kernel of the path: every element of the upper triangle is
+// read exactly once per step (8 bytes for 16 FP32 FMAs).
+//
+// Work item = tile row I and a run of up to kChunk tiles J0..J1-1.  Wave w of
+// the 256-thread workgroup owns rows 16w..16w+15 of each tile and lane l owns
+// column l, so row partial sums stay in registers across the run and are
+// reduced across lanes once per item; column partials are reduced across the
+// 4 waves per tile through LDS.  Every partial lands in its own slot
+// Q[target row][source] -- no floating-point atomics, so the result is
+// bitwise deterministic.  The workgroup that delivers the last partial of a
+// tile row (arrival counter) sums that row's slots in fixed order and applies
+// the shrink/momentum/power update for those 64 rows.
+#include "ofista_internal.h"
+
+namespace ofista {
+namespace {
+
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 x) {
+  // acc + a * x
+  acc.x = fmaf(a.x, x.x, acc.x);
+  acc.x = fmaf(-a.y, x.y, acc.x);
+  acc.y = fmaf(a.x, x.y, acc.y);
+  acc.y = fmaf(a.y, x.x, acc.y);
+  return acc;
+}
+
+__device__ __forceinline__ float2 cmac_conj(float2 acc, float2 a, float2 x) {
+  // acc + conj(a) * x
+  acc.x = fmaf(a.x, x.x, acc.x);
+  acc.x = fmaf(a.y, x.y, acc.x);
+  acc.y = fmaf(a.x, x.y, acc.y);
+  acc.y = fmaf(-a.y, x.x, acc.y);
+  return acc;
+}
+
+constexpr int kRowsPerWave = kTile / 4;  // 16
+
+// Last-arrival epilogue for tile row R: sum the slots, update 64 rows.
+__device__ void row_epilogue(const StepArgs &a, int R, float4 *red4, double *redd) {
+  const int nb = a.nb;
+  const int t = threadIdx.x;
+  const int r = t & 63, part = t >> 6;
+  // slots written this step for row R: columns j < R (column partials) and the
+  // run starts j = R, R + kChunk, ... (row partials)
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 *q = a.Q + static_cast<size_t>(R) * nb * kTile + r;
+  for (int j = part; j < nb; j += 4) {
+    if (j < R || ((j - R) % kChunk) == 0) {
+      const float4 v = q[static_cast<size_t>(j) * kTile];
+      acc.x += v.x;
+      acc.y += v.y;
+      acc.z += v.z;
+      acc.w += v.w;
+    }
+  }
+  red4[t] = acc;
+  __syncthreads();
+  if (t < 64) {
+    float4 s = red4[t];
+#pragma unroll
+    for (int p = 1; p < 4; ++p) {
+      const float4 v = red4[t + 64 * p];
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    // |w|^2 of the vector this step multiplied (fixed-order sum of the slots)
+    double wn2 = 0.0;
+    for (int j = 0; j < nb; ++j) wn2 += a.slot_prev[nb + j];
+    const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
+    const float tau = static_cast<float>(a.scal->tau);
+    const float alpha = static_cast<float>(a.scal->alpha);
+    const int i = R * kTile + t;
+    double rpart = 0.0, mpart = 0.0;
+    if (i < a.N) {
+      const float2 z = a.zc[i];
+      const float2 cold = a.cc[i];
+      const float2 bi = a.b[i];
+      const float2 w = a.wc[i];
+      const float gx = s.x - bi.x, gy = s.y - bi.y;
+      const float ux = z.x - tau * gx, uy = z.y - tau * gy;
+      const float mag = sqrtf(ux * ux + uy * uy);
+      float cx = 0.f, cy = 0.f;
+      if (mag > alpha) {
+        const float f = 1.f - alpha / mag;
+        cx = ux * f;
+        cy = uy * f;
+      }
+      a.cn[i] = make_float2(cx, cy);
+      a.zn[i] = make_float2(cx + a.beta * (cx - cold.x), cy + a.beta * (cy - cold.y));
+      const float2 wnext = make_float2(s.z * inv_wn, s.w * inv_wn);
+      a.wn[i] = wnext;
+      rpart = static_cast<double>(w.x) * s.z + static_cast<double>(w.y) * s.w;
+      mpart = static_cast<double>(wnext.x) * wnext.x + static_cast<double>(wnext.y) * wnext.y;
+    } else {
+      a.cn[i] = make_float2(0.f, 0.f);
+      a.zn[i] = make_float2(0.f, 0.f);
+      a.wn[i] = make_float2(0.f, 0.f);
+    }
+    redd[t] = rpart;
+    redd[64 + t] = mpart;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double rs = 0.0, ms = 0.0;
+    for (int k = 0; k < 64; ++k) {
+      rs += redd[k];
+      ms += redd[64 + k];
+    }
+    a.slot_cur[R] = rs;
+    a.slot_cur[nb + R] = ms;
+    a.cnt[R] = 0u;  // ready for the next step
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_fista_step(StepArgs a) {
+  __shared__ float4 colbuf[4][64];
+  __shared__ float4 red4[256];
+  __shared__ double redd[128];
+  __shared__ int last_list[kChunk + 1];
+  __shared__ int n_last;
+
+  const WorkItem it = a.items[blockIdx.x];
+  const int I = it.I, J0 = it.J0, J1 = it.J1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int row0 = wave * kRowsPerWave;
+
+  // z_I, w_I for this wave's 16 rows (wave-uniform)
+  float2 zI[kRowsPerWave], wI[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    zI[q] = a.zc[I * kTile + row0 + q];
+    wI[q] = a.wc[I * kTile + row0 + q];
+  }
+  float2 ryz[kRowsPerWave], ryw[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    ryz[q] = make_float2(0.f, 0.f);
+    ryw[q] = make_float2(0.f, 0.f);
+  }
+
+  const int trow = a.tile_row0[I];
+  for (int J = J0; J < J1; ++J) {
+    const float2 *Ht = a.H + static_cast<size_t>(trow + (J - I)) * (kTile * kTile) +
+                       row0 * kTile + lane;
+    float2 h[kRowsPerWave];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) h[q] = Ht[q * kTile];
+    const float2 zj = a.zc[J * kTile + lane];
+    const float2 wj = a.wc[J * kTile + lane];
+    float2 cz = make_float2(0.f, 0.f), cw = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      ryz[q] = cmac(ryz[q], h[q], zj);
+      ryw[q] = cmac(ryw[q], h[q], wj);
+      cz = cmac_conj(cz, h[q], zI[q]);
+      cw = cmac_conj(cw, h[q], wI[q]);
+    }
+    if (J != I) {
+      colbuf[wave][lane] = make_float4(cz.x, cz.y, cw.x, cw.y);
+      __syncthreads();
+      if (wave == 0) {
+        float4 s = colbuf[0][lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+          const float4 v = colbuf[w][lane];
+          s.x += v.x;
+          s.y += v.y;
+          s.z += v.z;
+          s.w += v.w;
+        }
+        a.Q[(static_cast<size_t>(J) * a.nb + I) * kTile + lane] = s;
+      }
+      __syncthreads();
+    }
+  }
+
+  // Row partials: 16 rows x (yz, yw) = 64 floats per lane, summed over the 64
+  // lanes by a halving butterfly; afterwards lane l holds element l
+  // (row l/4, component l%4).
+  float v[64];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    v[4 * q + 0] = ryz[q].x;
+    v[4 * q + 1] = ryz[q].y;
+    v[4 * q + 2] = ryw[q].x;
+    v[4 * q + 3] = ryw[q].y;
+  }
+#pragma unroll
+  for (int half = 32; half >= 1; half >>= 1) {
+    const bool upper = (lane & half) != 0;
+#pragma unroll
+    for (int e = 0; e < half; ++e) {
+      const float send = upper ? v[e] : v[e + half];
+      const float keep = upper ? v[e + half] : v[e];
+      v[e] = keep + __shfl_xor(send, half);
+    }
+  }
+  {
+    float *dst = reinterpret_cast<float *>(a.Q + (static_cast<size_t>(I) * a.nb + J0) * kTile + row0);
+    dst[lane] = v[0];
+  }
+
+  // publish, then count arrivals for every tile row this item fed
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int n = 0;
+    unsigned old = atomicAdd(&a.cnt[I], 1u);
+    if (old + 1u == a.expect[I]) last_list[n++] = I;
+    for (int J = J0; J < J1; ++J) {
+      if (J == I) continue;
+      old = atomicAdd(&a.cnt[J], 1u);
+      if (old + 1u == a.expect[J]) last_list[n++] = J;
+    }
+    n_last = n;
+  }
+  __syncthreads();
+  const int nl = n_last;
+  if (nl > 0) {
+    __threadfence();
+    for (int k = 0; k < nl; ++k) row_epilogue(a, last_list[k], red4, redd);
+  }
+}
+
+// Per-pulse scalars: lambda (first pulse), sigma^2 of position s, rho_{n-1}
+// from the power-vector slots, L_n, tau, alpha.  One thread.
+__global__ void k_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
+                          double lam_in, int lip, int have_rho, const double *slot_r,
+                          const double *slot_m, int nb) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (first) {
+    scal->lam = rel ? lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : lam_in;
+  }
+  const double sigma2 = sig2[s];
+  double rho = 0.0;
+  if (have_rho) {
+    double rs = 0.0, ms = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      rs += slot_r[j];
+      ms += slot_m[nb + j];
+    }
+    rho = rs / ms;
+  }
+  const double L = lip == 0 ? rho + sigma2 : scal->L + sigma2;
+  scal->sigma2 = sigma2;
+  scal->rho = rho;
+  scal->L = L;
+  scal->tau = 1.0 / L;
+  scal->alpha = scal->lam / L;
+}
+
+__global__ void k_fill(unsigned *p, size_t n, unsigned value) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = value;
+}
+
+// w_0 = 1/sqrt(N) on the real pixels; slot0 says |w_0|^2 = 1.
+__global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Npad) w[i] = make_float2(i < N ? static_cast<float>(1.0 / sqrt(static_cast<double>(N))) : 0.f, 0.f);
+  if (i < 2 * nb) {
+    slot0[i] = (i == nb) ? 1.0 : 0.0;
+    slot1[i] = 0.0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fista_step(const StepArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_fista_step, dim3(a.nitems), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
+                          double lam_in, int lip, int have_rho, const double *slot_r,
+                          const double *slot_m, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(64), 0, st, scal, sig2, s, first, rel, lam_in,
+                     lip, have_rho, slot_r, slot_m, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st) {
+  if (n_u32 == 0) return hipSuccess;
+  size_t blocks = (n_u32 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     static_cast<unsigned *>(p), n_u32, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nb,
+                             hipStream_t st) {
+  const int n = Npad > 2 * nb ? Npad : 2 * nb;
+  hipLaunchKernelGGL(k_init_power, dim3((n + 255) / 256), dim3(256), 0, st, w, slot0, slot1, N,
+                     Npad, nb);
+  return hipGetLastError();
+}
+
+}  // namespace ofista

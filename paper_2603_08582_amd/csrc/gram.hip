@@ -1,0 +1,209 @@
+// Sufficient-statistic updates of one pulse (Section III-C):
+//   b += A_s^H d~          (correlation; at the first pulse also max_i |Delta b_i|)
+//   H += A_s^H A_s         (rank-K Hermitian Gram update on the matrix cores)
+//
+// The Gram update is the one dense contraction on the path.  For a tile
+// (I, J) of H, with a = A_s[k, I-block] and a' = A_s[k, J-block] complex,
+//   Re H_ij += sum_k ar_i ar'_j + ai_i ai'_j,   Im H_ij += sum_k ar_i ai'_j - ai_i ar'_j.
+// v_mfma_f32_32x32x2f32 contracts two real terms per instruction, so one
+// frequency k is one instruction per output plane: the A operand of lane l is
+// (ar_i, ai_i)[l/32], the B operand (ar'_j, ai'_j)[l/32] for Re and
+// (ai'_j, -ar'_j)[l/32] for Im.  Only tiles with I <= J exist (packed upper
+// storage); the diagonal of each diagonal tile gets Im = 0 exactly.
+#include "ofista_internal.h"
+
+namespace ofista {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// b += A^H (d e^{-i phi}); optional block max of |Delta b| for lambda.
+__global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__ A,
+                                              const float2 *__restrict__ d,
+                                              float cphi, float sphi,
+                                              float2 *__restrict__ b,
+                                              DevScalars *__restrict__ scal, int first) {
+  extern __shared__ float2 dl[];  // K rotated samples
+  __shared__ float red[256];
+  for (int k = threadIdx.x; k < g.K; k += 256) {
+    const float2 v = d[k];
+    // d e^{-i phi} = (v.x + i v.y)(cos phi - i sin phi)
+    dl[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  float mag = 0.f;
+  if (i < g.Npad) {
+    float re = 0.f, im = 0.f;
+    const float2 *col = A + i;
+    for (int k = 0; k < g.K; ++k) {
+      const float2 a = col[static_cast<size_t>(k) * g.Npad];
+      const float2 x = dl[k];
+      // conj(a) * x
+      re += a.x * x.x + a.y * x.y;
+      im += a.x * x.y - a.y * x.x;
+    }
+    float2 bi = b[i];
+    bi.x += re;
+    bi.y += im;
+    b[i] = bi;
+    mag = sqrtf(re * re + im * im);
+  }
+  if (first) {
+    red[threadIdx.x] = mag;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    // max of non-negative floats: integer order equals float order
+    if (threadIdx.x == 0) atomicMax(&scal->dbmax_bits, __float_as_uint(red[0]));
+  }
+}
+
+// H(I, J) += A_I^H A_J for one 64 x 64 tile per workgroup, 4 waves each
+// owning a 32 x 32 quadrant.  Workgroup b runs on XCD b % 8; logical tile
+// (b % 8) * per + b / 8 keeps runs of neighbouring tiles (shared A blocks) on
+// one XCD's L2.
+__global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_grid,
+                                                   const float2 *__restrict__ A,
+                                                   const int2 *__restrict__ tile_ij,
+                                                   float2 *__restrict__ H) {
+  __shared__ float2 sa[kGramKB][kTile];
+  __shared__ float2 sb[kGramKB][kTile];
+  const int per = ntiles_grid >> 3;
+  const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int2 ij = tile_ij[logical];
+  if (ij.x < 0) return;  // padding of the grid to a multiple of 8
+  const int I = ij.x, J = ij.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  const bool hi = lane >= 32;
+  const int li = lane & 31;
+
+  floatx16 accR, accI;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accR[r] = 0.f;
+    accI[r] = 0.f;
+  }
+
+  // staging: kGramKB x 64 complex per operand = 512 float4; 2 per thread
+  const float4 *Ag = reinterpret_cast<const float4 *>(A);
+  const int rowf4 = Npad >> 1;  // float4 per A row
+  float4 pa[2], pb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int idx = threadIdx.x + r * 256;
+      const int kk = idx >> 5, c2 = idx & 31;
+      const int k = k0 + kk;
+      if (k < K) {
+        pa[r] = Ag[static_cast<size_t>(k) * rowf4 + I * (kTile / 2) + c2];
+        pb[r] = Ag[static_cast<size_t>(k) * rowf4 + J * (kTile / 2) + c2];
+      } else {
+        pa[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        pb[r] = pa[r];
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int idx = threadIdx.x + r * 256;
+      const int kk = idx >> 5, c2 = idx & 31;
+      reinterpret_cast<float4 *>(&sa[kk][0])[c2] = pa[r];
+      reinterpret_cast<float4 *>(&sb[kk][0])[c2] = pb[r];
+    }
+  };
+
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += kGramKB) {
+    const bool more = k0 + kGramKB < K;
+    if (more) gload(k0 + kGramKB);
+#pragma unroll
+    for (int kk = 0; kk < kGramKB; ++kk) {
+      const float2 a = sa[kk][wi * 32 + li];
+      const float2 c = sb[kk][wj * 32 + li];
+      const float av = hi ? a.y : a.x;
+      const float br = hi ? c.y : c.x;
+      const float bi = hi ? -c.x : c.y;
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(av, br, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bi, accI, 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      lstore();
+      __syncthreads();
+    }
+  }
+
+  // epilogue: read-modify-write of the packed tile.  Accumulator register r of
+  // lane l holds row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the quadrant.
+  size_t tile_index;
+  {
+    const int nb = Npad / kTile;
+    tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
+  }
+  float2 *Ht = H + tile_index * (kTile * kTile);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int col = wj * 32 + li;
+    float2 h = Ht[row * kTile + col];
+    h.x += accR[r];
+    h.y += accI[r];
+    if (I == J && row == col) h.y = 0.f;
+    Ht[row * kTile + col] = h;
+  }
+}
+
+// Dense N x N copy of the packed Hermitian H (inspection only).
+__global__ __launch_bounds__(256) void k_gram_dense(int N, int nb, const float2 *__restrict__ H,
+                                                    const int *__restrict__ tile_row0,
+                                                    float2 *__restrict__ out) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<size_t>(N) * N) return;
+  const int i = static_cast<int>(idx / N), j = static_cast<int>(idx % N);
+  const int I = i / kTile, J = j / kTile;
+  float2 v;
+  if (I <= J) {
+    v = H[static_cast<size_t>(tile_row0[I] + (J - I)) * kTile * kTile + (i % kTile) * kTile + (j % kTile)];
+  } else {
+    const float2 u = H[static_cast<size_t>(tile_row0[J] + (I - J)) * kTile * kTile + (j % kTile) * kTile + (i % kTile)];
+    v = make_float2(u.x, -u.y);
+  }
+  out[idx] = v;
+}
+
+}  // namespace
+
+hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
+                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
+                       int first, hipStream_t st) {
+  const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
+  hipLaunchKernelGGL(k_corr, dim3((g.Npad + 255) / 256), dim3(256), lds, st, g, A, d,
+                     static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
+                            const int2 *tile_ij, int ntiles_grid,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_fp32, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
+                     ntiles_grid, A, tile_ij, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_dense(const Geom &g, const float2 *H,
+                             const int *tile_row0, float2 *out,
+                             hipStream_t st) {
+  const size_t n = static_cast<size_t>(g.N) * g.N;
+  hipLaunchKernelGGL(k_gram_dense, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                     g.N, g.Npad / kTile, H, tile_row0, out);
+  return hipGetLastError();
+}
+
+}  // namespace ofista

@@ -1,0 +1,127 @@
+// Internal declarations of libofista: device-side layout constants, the
+// device scalar block, and the kernel launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ofista {
+
+// Edge of the square tiles of the packed Hermitian storage.  H is kept as
+// the nb(nb+1)/2 tiles (I, J), I <= J, of a zero-padded Npad x Npad matrix
+// (Npad = nb * kTile), each tile row-major, tiles in row-major upper order.
+constexpr int kTile = 64;
+// Tiles per FISTA work item (a run of tiles along one tile row).
+constexpr int kChunk = 4;
+// Frequencies staged per LDS step of the Gram update.
+constexpr int kGramKB = 16;
+
+constexpr double kC0 = 299792458.0;  // speed of light, m/s
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Scalars that live on the device because they depend on data.
+struct DevScalars {
+  double lam;           // l1 weight
+  double L;             // L_n
+  double tau;           // 1 / L_n
+  double alpha;         // lam * tau, the shrink threshold
+  double sigma2;        // ||A_s||_2^2 of the last pushed pulse
+  double rho;           // rho_{n-1} used for the last L_n
+  unsigned dbmax_bits;  // max_i |Delta b_i| of the first pulse, float bits
+  unsigned pad0;
+  double pad1[2];
+};
+
+// Geometry passed by value.
+struct Geom {
+  int nx, ny, N, Npad, K, npos;
+  double x0, y0, dx, dy;
+  double f0, df;
+};
+
+// One FISTA work item: tile row I, tiles J0 .. J1-1 (J0 >= I).
+struct WorkItem {
+  int I, J0, J1, pad;
+};
+
+// Device-side pointers of one context, carved from the workspace.
+struct DevState {
+  float2 *H;         // packed tiles
+  float2 *A;         // K x Npad rows of the current pulse (scratch)
+  float2 *b;
+  float2 *cbuf[2];   // c_hat, ping-pong by step parity
+  float2 *zbuf[2];   // momentum point z
+  float2 *wbuf[2];   // power vector
+  float4 *Q;         // matvec partials, nb x nb x kTile of (yz, yw)
+  unsigned *cnt;     // arrival counters per tile row (kept at 0 between launches)
+  unsigned *expect;  // arrivals per tile row per FISTA step
+  double *slots[2];  // per tile row: [0, nb) Re<w, Hw> parts, [nb, 2nb) |w'|^2 parts
+  DevScalars *scal;
+  double *pos;       // npos x 3
+  double *sig2;      // npos, ||A_s||_2^2 per position
+  double2 *gtoep;    // npos x K, Toeplitz generator of A_s A_s^H
+  int2 *tile_ij;     // logical tile -> (I, J), padded to a multiple of 8
+  int *tile_row0;    // index of tile (I, I)
+  WorkItem *items;
+  double2 *echo_tmp; // K clean-echo sums
+  // split-BF16 operands of the Gram update (NULL for FP32)
+  unsigned short *Ahi;
+  unsigned short *Alo;
+};
+
+// ---- rows.hip ----
+hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
+                       int dict, int levels, hipStream_t st);
+hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
+                        int levels, hipStream_t st);
+hipError_t launch_echo(const Geom &g, const double *pos, int s,
+                       const float2 *rho, const float2 *noise, double snr_db,
+                       double phase_err, double2 *tmp, float2 *out,
+                       hipStream_t st);
+hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
+                         double *sig2, hipStream_t st);
+
+// ---- gram.hip ----
+hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
+                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
+                       int first, hipStream_t st);
+hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
+                            const int2 *tile_ij, int ntiles_grid,
+                            hipStream_t st);
+hipError_t launch_gram_dense(const Geom &g, const float2 *H,
+                             const int *tile_row0, float2 *out,
+                             hipStream_t st);
+
+// ---- fista.hip ----
+struct StepArgs {
+  const float2 *H;
+  const float2 *zc;
+  const float2 *wc;
+  const float2 *b;
+  const float2 *cc;
+  float2 *cn;
+  float2 *zn;
+  float2 *wn;
+  float4 *Q;
+  unsigned *cnt;
+  const unsigned *expect;
+  const double *slot_prev;
+  double *slot_cur;
+  const DevScalars *scal;
+  const WorkItem *items;
+  const int *tile_row0;
+  int nb, N, nitems;
+  float beta;
+};
+hipError_t launch_fista_step(const StepArgs &a, hipStream_t st);
+hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
+                          int first, int rel, double lam_in, int lip,
+                          int have_rho, const double *slot_r,
+                          const double *slot_m, int nb, hipStream_t st);
+hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
+hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N,
+                             int Npad, int nb, hipStream_t st);
+
+}  // namespace ofista

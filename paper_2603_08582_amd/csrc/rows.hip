@@ -1,0 +1,354 @@
+// Forward-operator rows, dictionary fold, image synthesis, synthetic echo and
+// the per-position spectral norm ||A_s||_2^2.
+//
+// The kernel of F_s (Section II: amplitude 1, phase t - 2|gamma(s) - x|/c on a
+// stepped-frequency grid) is exp(-i 4 pi f_k R / c0).  At X band and 10 km the
+// phase is ~4e6 rad, where an FP32 ulp is 0.5 rad, so range and phase are
+// formed in FP64 and reduced modulo 2 pi in FP64 (two-constant Cody-Waite
+// split of 2 pi) before the FP32 sine/cosine.
+#include "ofista_internal.h"
+
+namespace ofista {
+namespace {
+
+constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+constexpr double k2PiHi = 6.283185307179586232;   // fl(2 pi)
+constexpr double k2PiLo = 2.4492935982947064e-16;  // 2 pi - fl(2 pi)
+
+__device__ __forceinline__ float2 phasor_neg(double phase) {
+  // exp(-i phase)
+  const double n = rint(phase * kInv2Pi);
+  double r = fma(-n, k2PiHi, phase);
+  r = fma(-n, k2PiLo, r);
+  float s, c;
+  sincosf(static_cast<float>(r), &s, &c);
+  return make_float2(c, -s);
+}
+
+__device__ __forceinline__ double pixel_range(const Geom &g, const double *p,
+                                              int i) {
+  const int ix = i % g.nx;
+  const int iy = i / g.nx;
+  const double ex = p[0] - (g.x0 + ix * g.dx);
+  const double ey = p[1] - (g.y0 + iy * g.dy);
+  const double ez = p[2];
+  return sqrt(ex * ex + ey * ey + ez * ez);
+}
+
+constexpr int kRowsKCh = 16;  // frequencies per thread in the identity rows
+
+// A_s = F_s for the identity dictionary: thread per pixel, kRowsKCh
+// frequencies per thread (the FP64 range is formed once per pixel).
+__global__ __launch_bounds__(256) void k_rows_identity(Geom g,
+                                                       const double *__restrict__ pos,
+                                                       int s,
+                                                       float2 *__restrict__ A) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int k0 = blockIdx.y * kRowsKCh;
+  if (i >= g.Npad) return;
+  const int kn = min(kRowsKCh, g.K - k0);
+  float2 *out = A + static_cast<size_t>(k0) * g.Npad + i;
+  if (i >= g.N) {
+    for (int kk = 0; kk < kn; ++kk) out[static_cast<size_t>(kk) * g.Npad] = make_float2(0.f, 0.f);
+    return;
+  }
+  const double R = pixel_range(g, pos + 3 * s, i);
+  const double c4 = 4.0 * kPi / kC0;
+  for (int kk = 0; kk < kn; ++kk) {
+    const double f = g.f0 + (k0 + kk) * g.df;
+    out[static_cast<size_t>(kk) * g.Npad] = phasor_neg((c4 * f) * R);
+  }
+}
+
+// One level of the orthonormal 2-D Haar analysis on the top-left m x m block
+// of an n-wide row-major image held in LDS, in place.  Each 2 x 2 input block
+// (a b / c d) produces  LL = (a+b+c+d)/2 at (y, x),  (a-b+c-d)/2 at (y, x+h),
+// (a+b-c-d)/2 at (y+h, x),  (a-b-c+d)/2 at (y+h, x+h),  h = m/2.
+template <int kMaxPer>
+__device__ void haar_level_analysis(float2 *buf, int n, int m) {
+  const int h = m >> 1;
+  const int nblk = h * h;
+  float2 o[kMaxPer][4];
+  int cnt = 0;
+  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+    const int y = q / h, x = q % h;
+    const float2 a = buf[(2 * y) * n + 2 * x];
+    const float2 b = buf[(2 * y) * n + 2 * x + 1];
+    const float2 c = buf[(2 * y + 1) * n + 2 * x];
+    const float2 d = buf[(2 * y + 1) * n + 2 * x + 1];
+    o[cnt][0] = make_float2(0.5f * ((a.x + b.x) + (c.x + d.x)), 0.5f * ((a.y + b.y) + (c.y + d.y)));
+    o[cnt][1] = make_float2(0.5f * ((a.x - b.x) + (c.x - d.x)), 0.5f * ((a.y - b.y) + (c.y - d.y)));
+    o[cnt][2] = make_float2(0.5f * ((a.x + b.x) - (c.x + d.x)), 0.5f * ((a.y + b.y) - (c.y + d.y)));
+    o[cnt][3] = make_float2(0.5f * ((a.x - b.x) - (c.x - d.x)), 0.5f * ((a.y - b.y) - (c.y - d.y)));
+  }
+  __syncthreads();
+  cnt = 0;
+  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+    const int y = q / h, x = q % h;
+    buf[y * n + x] = o[cnt][0];
+    buf[y * n + x + h] = o[cnt][1];
+    buf[(y + h) * n + x] = o[cnt][2];
+    buf[(y + h) * n + x + h] = o[cnt][3];
+  }
+  __syncthreads();
+}
+
+// Inverse of haar_level_analysis (the 4 x 4 map is its own inverse).
+template <int kMaxPer>
+__device__ void haar_level_synthesis(float2 *buf, int n, int m) {
+  const int h = m >> 1;
+  const int nblk = h * h;
+  float2 o[kMaxPer][4];
+  int cnt = 0;
+  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+    const int y = q / h, x = q % h;
+    const float2 ll = buf[y * n + x];
+    const float2 tr = buf[y * n + x + h];
+    const float2 bl = buf[(y + h) * n + x];
+    const float2 hh = buf[(y + h) * n + x + h];
+    o[cnt][0] = make_float2(0.5f * ((ll.x + tr.x) + (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) + (bl.y + hh.y)));
+    o[cnt][1] = make_float2(0.5f * ((ll.x - tr.x) + (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) + (bl.y - hh.y)));
+    o[cnt][2] = make_float2(0.5f * ((ll.x + tr.x) - (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) - (bl.y + hh.y)));
+    o[cnt][3] = make_float2(0.5f * ((ll.x - tr.x) - (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) - (bl.y - hh.y)));
+  }
+  __syncthreads();
+  cnt = 0;
+  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+    const int y = q / h, x = q % h;
+    buf[(2 * y) * n + 2 * x] = o[cnt][0];
+    buf[(2 * y) * n + 2 * x + 1] = o[cnt][1];
+    buf[(2 * y + 1) * n + 2 * x] = o[cnt][2];
+    buf[(2 * y + 1) * n + 2 * x + 1] = o[cnt][3];
+  }
+  __syncthreads();
+}
+
+constexpr int kHaarThreads = 1024;
+constexpr int kHaarMaxN = 8192;  // 64 KB of LDS per row image
+constexpr int kHaarMaxPer = kHaarMaxN / 4 / kHaarThreads;  // 2x2 blocks per thread
+
+// A_s = F_s W for the Haar dictionary: one workgroup per frequency row; the
+// row, viewed as an n x n image, is formed in LDS and analysed level by level
+// (W^T applied to each row, since W is the orthonormal synthesis matrix).
+__global__ __launch_bounds__(kHaarThreads) void k_rows_haar(Geom g,
+                                                            const double *__restrict__ pos,
+                                                            int s, int levels,
+                                                            float2 *__restrict__ A) {
+  extern __shared__ float2 buf[];
+  const int k = blockIdx.x;
+  const double c4f = (4.0 * kPi / kC0) * (g.f0 + k * g.df);
+  const double *p = pos + 3 * s;
+  for (int i = threadIdx.x; i < g.N; i += kHaarThreads) {
+    buf[i] = phasor_neg(c4f * pixel_range(g, p, i));
+  }
+  __syncthreads();
+  for (int lev = 0; lev < levels; ++lev) haar_level_analysis<kHaarMaxPer>(buf, g.nx, g.nx >> lev);
+  float2 *out = A + static_cast<size_t>(k) * g.Npad;
+  for (int i = threadIdx.x; i < g.Npad; i += kHaarThreads)
+    out[i] = i < g.N ? buf[i] : make_float2(0.f, 0.f);
+}
+
+// x = W c for the Haar dictionary (single workgroup).
+__global__ __launch_bounds__(kHaarThreads) void k_image_haar(Geom g, int levels,
+                                                             const float2 *__restrict__ c,
+                                                             float2 *__restrict__ x) {
+  extern __shared__ float2 buf[];
+  for (int i = threadIdx.x; i < g.N; i += kHaarThreads) buf[i] = c[i];
+  __syncthreads();
+  for (int lev = levels - 1; lev >= 0; --lev) haar_level_synthesis<kHaarMaxPer>(buf, g.nx, g.nx >> lev);
+  for (int i = threadIdx.x; i < g.N; i += kHaarThreads) x[i] = buf[i];
+}
+
+__global__ void k_copy_c64(const float2 *__restrict__ src, float2 *__restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// Fixed-order tree sum over a 256-thread block of double2 values.
+__device__ double2 block_sum_d2(double2 v, double2 *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[threadIdx.x].x += red[threadIdx.x + off].x;
+      red[threadIdx.x].y += red[threadIdx.x + off].y;
+    }
+    __syncthreads();
+  }
+  const double2 r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Clean echo sum_i F_s[k, i] rho_i, one workgroup per frequency (FP64 sums).
+__global__ __launch_bounds__(256) void k_echo_clean(Geom g, const double *__restrict__ pos,
+                                                    int s, const float2 *__restrict__ rho,
+                                                    double2 *__restrict__ tmp) {
+  __shared__ double2 red[256];
+  const int k = blockIdx.x;
+  const double c4f = (4.0 * kPi / kC0) * (g.f0 + k * g.df);
+  const double *p = pos + 3 * s;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < g.N; i += 256) {
+    const float2 r = rho[i];
+    if (r.x == 0.f && r.y == 0.f) continue;
+    const float2 e = phasor_neg(c4f * pixel_range(g, p, i));
+    acc.x += static_cast<double>(e.x) * r.x - static_cast<double>(e.y) * r.y;
+    acc.y += static_cast<double>(e.x) * r.y + static_cast<double>(e.y) * r.x;
+  }
+  const double2 t = block_sum_d2(acc, red);
+  if (threadIdx.x == 0) tmp[k] = t;
+}
+
+// d = exp(i phase_err) clean + sigma noise, sigma^2 = |clean|^2 / K 10^(-snr/10).
+__global__ __launch_bounds__(256) void k_echo_finish(int K, const double2 *__restrict__ tmp,
+                                                     const float2 *__restrict__ noise,
+                                                     double snr_db, double cph, double sph,
+                                                     float2 *__restrict__ out) {
+  __shared__ double2 red[256];
+  double2 e = make_double2(0.0, 0.0);
+  for (int k = threadIdx.x; k < K; k += 256) e.x += tmp[k].x * tmp[k].x + tmp[k].y * tmp[k].y;
+  const double energy = block_sum_d2(e, red).x;
+  const double sigma = noise ? sqrt(energy / K * pow(10.0, -snr_db / 10.0)) : 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const double2 c = tmp[k];
+    double re = cph * c.x - sph * c.y;
+    double im = cph * c.y + sph * c.x;
+    if (noise) {
+      re += sigma * noise[k].x;
+      im += sigma * noise[k].y;
+    }
+    out[k] = make_float2(static_cast<float>(re), static_cast<float>(im));
+  }
+}
+
+constexpr int kToepDCh = 8;  // lags per workgroup
+
+// Toeplitz generator of A_s A_s^H for a uniform frequency grid:
+// (A_s A_s^H)[k, l] = g(k - l), g(d) = sum_i exp(-i 4 pi d df R_i / c0), g(-d) = conj(g(d)).
+// W W^T = I for both dictionaries, so the pixel-domain kernel suffices.
+__global__ __launch_bounds__(256) void k_toeplitz(Geom g, const double *__restrict__ pos,
+                                                  double2 *__restrict__ gtoep) {
+  __shared__ double2 red[256];
+  const int s = blockIdx.x;
+  const int d0 = blockIdx.y * kToepDCh;
+  const double *p = pos + 3 * s;
+  const double c4d = 4.0 * kPi / kC0 * g.df;
+  double2 acc[kToepDCh];
+#pragma unroll
+  for (int j = 0; j < kToepDCh; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < g.N; i += 256) {
+    const double R = pixel_range(g, p, i);
+#pragma unroll
+    for (int j = 0; j < kToepDCh; ++j) {
+      const float2 e = phasor_neg((c4d * (d0 + j)) * R);
+      acc[j].x += e.x;
+      acc[j].y += e.y;
+    }
+  }
+  for (int j = 0; j < kToepDCh; ++j) {
+    const double2 t = block_sum_d2(acc[j], red);
+    if (threadIdx.x == 0 && d0 + j < g.K) gtoep[static_cast<size_t>(s) * g.K + d0 + j] = t;
+  }
+}
+
+constexpr int kPowerMaxSteps = 200;
+constexpr double kPowerRelTol = 1e-13;
+
+// sigma^2 = lambda_max(A_s A_s^H) by FP64 power iteration, one workgroup per
+// position: v0 = 1/sqrt(K); y = M v, q = Re(v^H y); stop when |q - q_prev| <=
+// 1e-13 |q| or after 200 steps; otherwise v = y / |y|.
+__global__ __launch_bounds__(256) void k_power_sigma2(int K, const double2 *__restrict__ gtoep,
+                                                      double *__restrict__ sig2) {
+  extern __shared__ double2 sh[];
+  double2 *gl = sh;          // K
+  double2 *v = sh + K;       // K
+  double2 *y = sh + 2 * K;   // K
+  __shared__ double2 red[256];
+  __shared__ int done;
+  const int s = blockIdx.x;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    gl[k] = gtoep[static_cast<size_t>(s) * K + k];
+    v[k] = make_double2(1.0 / sqrt(static_cast<double>(K)), 0.0);
+  }
+  if (threadIdx.x == 0) done = 0;
+  __syncthreads();
+  double q = 0.0, q_prev = 0.0;
+  for (int step = 0; step < kPowerMaxSteps; ++step) {
+    double2 part = make_double2(0.0, 0.0);  // (Re v^H y, |y|^2)
+    for (int k = threadIdx.x; k < K; k += 256) {
+      double re = 0.0, im = 0.0;
+      for (int l = 0; l <= k; ++l) {  // M[k, l] = g(k - l)
+        const double2 m = gl[k - l], x = v[l];
+        re += m.x * x.x - m.y * x.y;
+        im += m.x * x.y + m.y * x.x;
+      }
+      for (int l = k + 1; l < K; ++l) {  // M[k, l] = conj(g(l - k))
+        const double2 m = gl[l - k], x = v[l];
+        re += m.x * x.x + m.y * x.y;
+        im += m.x * x.y - m.y * x.x;
+      }
+      y[k] = make_double2(re, im);
+      part.x += v[k].x * re + v[k].y * im;
+      part.y += re * re + im * im;
+    }
+    const double2 tot = block_sum_d2(part, red);
+    q = tot.x;
+    if (threadIdx.x == 0) {
+      if ((step > 0 && fabs(q - q_prev) <= kPowerRelTol * fabs(q)) || tot.y == 0.0) done = 1;
+    }
+    __syncthreads();
+    if (done) break;
+    q_prev = q;
+    const double inv = 1.0 / sqrt(tot.y);
+    for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(y[k].x * inv, y[k].y * inv);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sig2[s] = q;
+}
+
+}  // namespace
+
+hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
+                       int dict, int levels, hipStream_t st) {
+  if (dict == 1) {
+    const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
+    hipLaunchKernelGGL(k_rows_haar, dim3(g.K), dim3(kHaarThreads), lds, st, g, pos, s, levels, A);
+  } else {
+    dim3 grid((g.Npad + 255) / 256, (g.K + kRowsKCh - 1) / kRowsKCh);
+    hipLaunchKernelGGL(k_rows_identity, grid, dim3(256), 0, st, g, pos, s, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
+                        int levels, hipStream_t st) {
+  if (dict == 1) {
+    const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
+    hipLaunchKernelGGL(k_image_haar, dim3(1), dim3(kHaarThreads), lds, st, g, levels, c, x);
+  } else {
+    hipLaunchKernelGGL(k_copy_c64, dim3((g.N + 255) / 256), dim3(256), 0, st, c, x, g.N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_echo(const Geom &g, const double *pos, int s,
+                       const float2 *rho, const float2 *noise, double snr_db,
+                       double phase_err, double2 *tmp, float2 *out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_echo_clean, dim3(g.K), dim3(256), 0, st, g, pos, s, rho, tmp);
+  hipLaunchKernelGGL(k_echo_finish, dim3(1), dim3(256), 0, st, g.K, tmp, noise, snr_db,
+                     cos(phase_err), sin(phase_err), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
+                         double *sig2, hipStream_t st) {
+  dim3 grid(g.npos, (g.K + kToepDCh - 1) / kToepDCh);
+  hipLaunchKernelGGL(k_toeplitz, grid, dim3(256), 0, st, g, pos, gtoep);
+  const size_t lds = 3 * static_cast<size_t>(g.K) * sizeof(double2);
+  hipLaunchKernelGGL(k_power_sigma2, dim3(g.npos), dim3(256), lds, st, g.K, gtoep, sig2);
+  return hipGetLastError();
+}
+
+}  // namespace ofista

@@ -1,0 +1,655 @@
+// Host runtime of libofista: configuration checks, workspace layout, the
+// per-pulse launch sequence and the C ABI declared in include/ofista.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ofista.h"
+#include "ofista_internal.h"
+
+using namespace ofista;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int N = 0, Npad = 0, nb = 0, K = 0, npos = 0;
+  size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
+  // byte offsets
+  size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, cnt, expect, slot0, slot1, scal, pos,
+      sig2, gtoep, tile_ij, tile_row0, items, echo_tmp, Ahi, Alo;
+  size_t total = 0;
+};
+
+size_t count_items(int nb) {
+  size_t n = 0;
+  for (int I = 0; I < nb; ++I) n += static_cast<size_t>((nb - I + kChunk - 1) / kChunk);
+  return n;
+}
+
+ofista_status check(const ofista_config *c, std::string *why) {
+  auto bad = [&](const char *m) {
+    if (why) *why = m;
+    return OFISTA_E_ARG;
+  };
+  if (!c) return bad("config is NULL");
+  if (c->n_x < 1 || c->n_y < 1) return bad("n_x and n_y must be >= 1");
+  const long long N = static_cast<long long>(c->n_x) * c->n_y;
+  if (N > (1LL << 18)) return bad("N = n_x*n_y must be <= 262144");
+  if (!std::isfinite(c->x0) || !std::isfinite(c->y0) || !std::isfinite(c->dx) ||
+      !std::isfinite(c->dy))
+    return bad("grid origin and spacing must be finite");
+  if (c->n_pos < 1) return bad("n_pos must be >= 1");
+  if (!c->pos_xyz) return bad("pos_xyz is NULL");
+  if (c->n_freq < 1 || c->n_freq > 1024) return bad("n_freq must be in [1, 1024]");
+  if (!std::isfinite(c->freq0_hz) || !std::isfinite(c->dfreq_hz))
+    return bad("frequencies must be finite");
+  if (c->dict != OFISTA_DICT_IDENTITY && c->dict != OFISTA_DICT_HAAR2D) return bad("unknown dict");
+  if (c->dict == OFISTA_DICT_HAAR2D) {
+    if (c->haar_levels < 1) return bad("haar_levels must be >= 1");
+    if (c->n_x != c->n_y) return bad("Haar dictionary needs a square grid");
+    if (c->haar_levels > 14 || c->n_x % (1 << c->haar_levels) != 0)
+      return bad("n_x must be divisible by 2^haar_levels");
+    if (N > 8192) {
+      if (why) *why = "Haar dictionary is limited to N <= 8192";
+      return OFISTA_E_UNSUPPORTED;
+    }
+  }
+  if (!std::isfinite(c->lambda) || c->lambda < 0) return bad("lambda must be finite and >= 0");
+  if (c->precision != OFISTA_PREC_FP32 && c->precision != OFISTA_PREC_SPLIT_BF16)
+    return bad("unknown precision");
+  if (c->lipschitz != OFISTA_LIP_RUNNING && c->lipschitz != OFISTA_LIP_BOUND)
+    return bad("unknown lipschitz rule");
+  if (c->momentum < OFISTA_MOMENTUM_FISTA || c->momentum > OFISTA_MOMENTUM_ISTA)
+    return bad("unknown momentum mode");
+  if (c->record_every < 0) return bad("record_every must be >= 0");
+  if (c->precision == OFISTA_PREC_SPLIT_BF16) {
+    if (why) *why = "split-BF16 Gram update not available in this build";
+    return OFISTA_E_UNSUPPORTED;
+  }
+  if (c->record_every > 0) {
+    if (why) *why = "recording for backward not available in this build";
+    return OFISTA_E_UNSUPPORTED;
+  }
+  for (int i = 0; i < 3 * c->n_pos; ++i)
+    if (!std::isfinite(c->pos_xyz[i])) return bad("pos_xyz must be finite");
+  return OFISTA_OK;
+}
+
+Layout layout(const ofista_config *c) {
+  Layout L;
+  L.N = c->n_x * c->n_y;
+  L.nb = (L.N + kTile - 1) / kTile;
+  L.Npad = L.nb * kTile;
+  L.K = c->n_freq;
+  L.npos = c->n_pos;
+  L.ntiles = static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
+  L.ntiles_grid = (L.ntiles + 7) / 8 * 8;
+  L.nitems = count_items(L.nb);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t vec = static_cast<size_t>(L.Npad) * sizeof(float2);
+  L.H = take(L.ntiles * kTile * kTile * sizeof(float2));
+  L.A = take(static_cast<size_t>(L.K) * L.Npad * sizeof(float2));
+  L.b = take(vec);
+  L.c0 = take(vec);
+  L.c1 = take(vec);
+  L.z0 = take(vec);
+  L.z1 = take(vec);
+  L.w0 = take(vec);
+  L.w1 = take(vec);
+  L.Q = take(static_cast<size_t>(L.nb) * L.nb * kTile * sizeof(float4));
+  L.cnt = take(L.nb * sizeof(unsigned));
+  L.expect = take(L.nb * sizeof(unsigned));
+  L.slot0 = take(2 * L.nb * sizeof(double));
+  L.slot1 = take(2 * L.nb * sizeof(double));
+  L.scal = take(sizeof(DevScalars));
+  L.pos = take(3 * static_cast<size_t>(L.npos) * sizeof(double));
+  L.sig2 = take(L.npos * sizeof(double));
+  L.gtoep = take(static_cast<size_t>(L.npos) * L.K * sizeof(double2));
+  L.tile_ij = take(L.ntiles_grid * sizeof(int2));
+  L.tile_row0 = take(L.nb * sizeof(int));
+  L.items = take(L.nitems * sizeof(WorkItem));
+  L.echo_tmp = take(L.K * sizeof(double2));
+  L.Ahi = L.Alo = 0;
+  L.total = o;
+  return L;
+}
+
+const char *status_text(ofista_status st) {
+  switch (st) {
+    case OFISTA_OK: return "ok";
+    case OFISTA_E_ARG: return "invalid argument";
+    case OFISTA_E_RANGE: return "pulse index out of range";
+    case OFISTA_E_STATE: return "call not valid in the current state";
+    case OFISTA_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case OFISTA_E_UNSUPPORTED: return "unsupported configuration";
+    case OFISTA_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+enum ProfClass { kProfGram = 0, kProfStep = 1, kProfRows = 2, kProfCorr = 3, kProfScalars = 4, kProfN = 5 };
+
+}  // namespace
+
+struct ofista_ctx {
+  ofista_config cfg{};
+  Layout L;
+  Geom g{};
+  DevState d{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  bool poisoned = false;
+  hipError_t hip_err = hipSuccess;
+  std::string msg;
+  // host-side state (all data independent)
+  int64_t n = 0;       // pulses since reset
+  int64_t G = 0;       // FISTA steps since reset
+  bool have_iter = false;
+  double t = 1.0;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+ofista_status fail_hip(ofista_ctx *c, hipError_t e, const char *where) {
+  c->poisoned = true;
+  c->hip_err = e;
+  c->msg = std::string(where) + ": " + hipGetErrorString(e);
+  return OFISTA_E_HIP;
+}
+
+#define OF_CK(ctx, expr)                                      \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return fail_hip((ctx), e_, #expr); \
+  } while (0)
+
+ofista_status usable(ofista_ctx *c) {
+  if (!c) return OFISTA_E_ARG;
+  if (c->poisoned) return OFISTA_E_STATE;
+  return OFISTA_OK;
+}
+
+hipEvent_t take_event(ofista_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one launch with events when profiling.
+struct ProfScope {
+  ofista_ctx *c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(ofista_ctx *ctx, int k) : c(ctx), cls(k) {
+    if (c->prof) {
+      a = take_event(c);
+      b = take_event(c);
+      if (a && b) hipEventRecord(a, c->st);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof && a && b) {
+      hipEventRecord(b, c->st);
+      c->ev.push_back({cls, {a, b}});
+    }
+  }
+};
+
+ofista_status do_reset(ofista_ctx *c) {
+  const Layout &L = c->L;
+  const DevState &d = c->d;
+  const size_t vecw = static_cast<size_t>(L.Npad) * 2;  // u32 words per vector
+  OF_CK(c, launch_fill(d.H, L.ntiles * kTile * kTile * 2, 0u, c->st));
+  OF_CK(c, launch_fill(d.b, vecw, 0u, c->st));
+  for (int p = 0; p < 2; ++p) {
+    OF_CK(c, launch_fill(d.cbuf[p], vecw, 0u, c->st));
+    OF_CK(c, launch_fill(d.zbuf[p], vecw, 0u, c->st));
+  }
+  OF_CK(c, launch_fill(d.wbuf[1], vecw, 0u, c->st));
+  OF_CK(c, launch_fill(d.cnt, L.nb, 0u, c->st));
+  OF_CK(c, launch_fill(d.scal, sizeof(DevScalars) / 4, 0u, c->st));
+  OF_CK(c, launch_init_power(d.wbuf[0], d.slots[0], d.slots[1], L.N, L.Npad, L.nb, c->st));
+  c->n = 0;
+  c->G = 0;
+  c->have_iter = false;
+  c->t = 1.0;
+  return OFISTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ofista_tile(void) { return kTile; }
+
+ofista_status ofista_check_config(const ofista_config *cfg) { return check(cfg, nullptr); }
+
+size_t ofista_workspace_bytes(const ofista_config *cfg) {
+  if (check(cfg, nullptr) != OFISTA_OK) return 0;
+  return layout(cfg).total;
+}
+
+size_t ofista_state_bytes(const ofista_config *cfg) {
+  if (check(cfg, nullptr) != OFISTA_OK) return 0;
+  const Layout L = layout(cfg);
+  return align_up(16 * sizeof(double)) + align_up(sizeof(DevScalars)) +
+         2 * align_up(2 * L.nb * sizeof(double)) +
+         3 * align_up(static_cast<size_t>(L.Npad) * sizeof(float2)) +
+         L.ntiles * kTile * kTile * sizeof(float2);
+}
+
+ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t ws_bytes,
+                            void *hip_stream, ofista_ctx **out) {
+  if (!out) return OFISTA_E_ARG;
+  *out = nullptr;
+  ofista_status st = check(cfg, nullptr);
+  if (st != OFISTA_OK) return st;
+  const Layout L = layout(cfg);
+  if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign != 0 ||
+      ws_bytes < L.total)
+    return OFISTA_E_WORKSPACE;
+  ofista_ctx *c = new (std::nothrow) ofista_ctx();
+  if (!c) return OFISTA_E_ARG;
+  c->cfg = *cfg;
+  c->cfg.pos_xyz = nullptr;  // host table is not kept
+  c->L = L;
+  c->st = static_cast<hipStream_t>(hip_stream);
+  Geom &g = c->g;
+  g.nx = cfg->n_x;
+  g.ny = cfg->n_y;
+  g.N = L.N;
+  g.Npad = L.Npad;
+  g.K = L.K;
+  g.npos = L.npos;
+  g.x0 = cfg->x0;
+  g.y0 = cfg->y0;
+  g.dx = cfg->dx;
+  g.dy = cfg->dy;
+  g.f0 = cfg->freq0_hz;
+  g.df = cfg->dfreq_hz;
+
+  char *base = static_cast<char *>(d_workspace);
+  DevState &d = c->d;
+  d.H = reinterpret_cast<float2 *>(base + L.H);
+  d.A = reinterpret_cast<float2 *>(base + L.A);
+  d.b = reinterpret_cast<float2 *>(base + L.b);
+  d.cbuf[0] = reinterpret_cast<float2 *>(base + L.c0);
+  d.cbuf[1] = reinterpret_cast<float2 *>(base + L.c1);
+  d.zbuf[0] = reinterpret_cast<float2 *>(base + L.z0);
+  d.zbuf[1] = reinterpret_cast<float2 *>(base + L.z1);
+  d.wbuf[0] = reinterpret_cast<float2 *>(base + L.w0);
+  d.wbuf[1] = reinterpret_cast<float2 *>(base + L.w1);
+  d.Q = reinterpret_cast<float4 *>(base + L.Q);
+  d.cnt = reinterpret_cast<unsigned *>(base + L.cnt);
+  d.expect = reinterpret_cast<unsigned *>(base + L.expect);
+  d.slots[0] = reinterpret_cast<double *>(base + L.slot0);
+  d.slots[1] = reinterpret_cast<double *>(base + L.slot1);
+  d.scal = reinterpret_cast<DevScalars *>(base + L.scal);
+  d.pos = reinterpret_cast<double *>(base + L.pos);
+  d.sig2 = reinterpret_cast<double *>(base + L.sig2);
+  d.gtoep = reinterpret_cast<double2 *>(base + L.gtoep);
+  d.tile_ij = reinterpret_cast<int2 *>(base + L.tile_ij);
+  d.tile_row0 = reinterpret_cast<int *>(base + L.tile_row0);
+  d.items = reinterpret_cast<WorkItem *>(base + L.items);
+  d.echo_tmp = reinterpret_cast<double2 *>(base + L.echo_tmp);
+
+  // host tables
+  const int nb = L.nb;
+  std::vector<int2> tij(L.ntiles_grid, make_int2(-1, -1));
+  std::vector<int> row0(nb);
+  {
+    size_t t = 0;
+    for (int I = 0; I < nb; ++I) {
+      row0[I] = static_cast<int>(t);
+      for (int J = I; J < nb; ++J) tij[t++] = make_int2(I, J);
+    }
+  }
+  std::vector<WorkItem> items;
+  items.reserve(L.nitems);
+  std::vector<unsigned> expect(nb);
+  for (int I = 0; I < nb; ++I) {
+    int nchunks = 0;
+    for (int J0 = I; J0 < nb; J0 += kChunk) {
+      items.push_back(WorkItem{I, J0, J0 + kChunk < nb ? J0 + kChunk : nb, 0});
+      ++nchunks;
+    }
+    expect[I] = static_cast<unsigned>(I + nchunks);
+  }
+
+  auto fail = [&](hipError_t e, const char *where) {
+    fail_hip(c, e, where);
+    *out = c;  // hand back the poisoned ctx so the caller can read the message
+    return OFISTA_E_HIP;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) return fail(e, "hipGetDevice");
+  if ((e = hipMemcpyAsync(d.pos, cfg->pos_xyz, 3 * sizeof(double) * L.npos, hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy positions");
+  if ((e = hipMemcpyAsync(d.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy tile table");
+  if ((e = hipMemcpyAsync(d.tile_row0, row0.data(), row0.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy tile rows");
+  if ((e = hipMemcpyAsync(d.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy work items");
+  if ((e = hipMemcpyAsync(d.expect, expect.data(), expect.size() * sizeof(unsigned), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy arrival counts");
+  if ((e = launch_sigma2(g, d.pos, d.gtoep, d.sig2, c->st)) != hipSuccess) return fail(e, "sigma2 kernels");
+  st = do_reset(c);
+  if (st != OFISTA_OK) {
+    *out = c;
+    return st;
+  }
+  if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+  *out = c;
+  return OFISTA_OK;
+}
+
+ofista_status ofista_reset(ofista_ctx *c) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  return do_reset(c);
+}
+
+ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_pulse || !std::isfinite(phase_corr)) return OFISTA_E_ARG;
+  if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
+  const DevState &d = c->d;
+  const int first = c->n == 0 ? 1 : 0;
+  {
+    ProfScope p(c, kProfRows);
+    OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
+  }
+  {
+    ProfScope p(c, kProfCorr);
+    OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
+                         std::sin(phase_corr), d.b, d.scal, first, c->st));
+  }
+  {
+    ProfScope p(c, kProfGram);
+    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(c->L.ntiles_grid), c->st));
+  }
+  {
+    ProfScope p(c, kProfScalars);
+    const int par = static_cast<int>(c->G & 1);
+    OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
+                            c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
+                            c->L.nb, c->st));
+  }
+  c->n += 1;
+  return OFISTA_OK;
+}
+
+ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (iters < 0) return OFISTA_E_ARG;
+  if (c->n == 0) return OFISTA_E_STATE;
+  const DevState &d = c->d;
+  double t = (c->n == 1 || c->cfg.momentum == OFISTA_MOMENTUM_RESTART) ? 1.0 : c->t;
+  for (int k = 0; k < iters; ++k) {
+    const int p = static_cast<int>(c->G & 1);
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double beta = c->cfg.momentum == OFISTA_MOMENTUM_ISTA ? 0.0 : (t - 1.0) / tn;
+    StepArgs a{};
+    a.H = d.H;
+    a.zc = k == 0 ? d.cbuf[p] : d.zbuf[p];
+    a.wc = d.wbuf[p];
+    a.b = d.b;
+    a.cc = d.cbuf[p];
+    a.cn = d.cbuf[p ^ 1];
+    a.zn = d.zbuf[p ^ 1];
+    a.wn = d.wbuf[p ^ 1];
+    a.Q = d.Q;
+    a.cnt = d.cnt;
+    a.expect = d.expect;
+    a.slot_prev = d.slots[p];
+    a.slot_cur = d.slots[p ^ 1];
+    a.scal = d.scal;
+    a.items = d.items;
+    a.tile_row0 = d.tile_row0;
+    a.nb = c->L.nb;
+    a.N = c->L.N;
+    a.nitems = static_cast<int>(c->L.nitems);
+    a.beta = static_cast<float>(beta);
+    {
+      ProfScope ps(c, kProfStep);
+      OF_CK(c, launch_fista_step(a, c->st));
+    }
+    c->G += 1;
+    t = tn;
+  }
+  c->t = t;
+  if (iters > 0) c->have_iter = true;
+  if (d_coef_out) {
+    OF_CK(c, hipMemcpyAsync(d_coef_out, d.cbuf[c->G & 1], static_cast<size_t>(c->L.N) * sizeof(float2),
+                            hipMemcpyDeviceToDevice, c->st));
+  }
+  return OFISTA_OK;
+}
+
+ofista_status ofista_image(ofista_ctx *c, void *d_img_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_img_out) return OFISTA_E_ARG;
+  OF_CK(c, launch_image(c->g, c->d.cbuf[c->G & 1], static_cast<float2 *>(d_img_out), c->cfg.dict,
+                        c->cfg.haar_levels, c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_vector(ofista_ctx *c, int32_t which, void *d_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_out || which < 0 || which > 2) return OFISTA_E_ARG;
+  const float2 *src = which == 0 ? c->d.b : which == 1 ? c->d.cbuf[c->G & 1] : c->d.wbuf[c->G & 1];
+  OF_CK(c, hipMemcpyAsync(d_out, src, static_cast<size_t>(c->L.N) * sizeof(float2),
+                          hipMemcpyDeviceToDevice, c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_rows(ofista_ctx *c, int32_t s, void *d_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_out) return OFISTA_E_ARG;
+  if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
+  OF_CK(c, launch_rows(c->g, c->d.pos, s, c->d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
+  OF_CK(c, hipMemcpy2DAsync(d_out, static_cast<size_t>(c->L.N) * sizeof(float2), c->d.A,
+                            static_cast<size_t>(c->L.Npad) * sizeof(float2),
+                            static_cast<size_t>(c->L.N) * sizeof(float2), c->L.K,
+                            hipMemcpyDeviceToDevice, c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_gram(ofista_ctx *c, void *d_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_out) return OFISTA_E_ARG;
+  if (c->L.N > 16384) return OFISTA_E_UNSUPPORTED;  // inspection of small problems only
+  OF_CK(c, launch_gram_dense(c->g, c->d.H, c->d.tile_row0, static_cast<float2 *>(d_out), c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_echo(ofista_ctx *c, int32_t s, const void *d_rho, const void *d_noise,
+                          double snr_db, double phase_err, void *d_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_rho || !d_out || !std::isfinite(snr_db) || !std::isfinite(phase_err)) return OFISTA_E_ARG;
+  if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
+  OF_CK(c, launch_echo(c->g, c->d.pos, s, static_cast<const float2 *>(d_rho),
+                       static_cast<const float2 *>(d_noise), snr_db, phase_err, c->d.echo_tmp,
+                       static_cast<float2 *>(d_out), c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_state(ofista_ctx *c, ofista_stats *out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!out) return OFISTA_E_ARG;
+  DevScalars s{};
+  const int nb = c->L.nb;
+  std::vector<double> sr(2 * nb), sm(2 * nb);
+  const int par = static_cast<int>(c->G & 1);
+  OF_CK(c, hipStreamSynchronize(c->st));
+  OF_CK(c, hipMemcpy(&s, c->d.scal, sizeof(s), hipMemcpyDeviceToHost));
+  OF_CK(c, hipMemcpy(sr.data(), c->d.slots[par], 2 * nb * sizeof(double), hipMemcpyDeviceToHost));
+  OF_CK(c, hipMemcpy(sm.data(), c->d.slots[par ^ 1], 2 * nb * sizeof(double), hipMemcpyDeviceToHost));
+  double rho = 0.0;
+  if (c->have_iter) {
+    double rs = 0.0, ms = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      rs += sr[j];
+      ms += sm[nb + j];
+    }
+    rho = rs / ms;
+  }
+  out->n_pulses = c->n;
+  out->n_iters = c->G;
+  out->t = c->t;
+  out->L = s.L;
+  out->tau = s.tau;
+  out->lambda = s.lam;
+  out->rho = rho;
+  out->sigma2 = s.sigma2;
+  return OFISTA_OK;
+}
+
+ofista_status ofista_export_state(ofista_ctx *c, void *d_buf) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_buf) return OFISTA_E_ARG;
+  const Layout &L = c->L;
+  const int par = static_cast<int>(c->G & 1);
+  double hdr[16] = {0};
+  hdr[0] = static_cast<double>(c->n);
+  hdr[1] = static_cast<double>(c->G);
+  hdr[2] = c->t;
+  hdr[3] = c->have_iter ? 1.0 : 0.0;
+  hdr[4] = static_cast<double>(L.N);
+  hdr[5] = static_cast<double>(L.K);
+  char *o = static_cast<char *>(d_buf);
+  const size_t vec = static_cast<size_t>(L.Npad) * sizeof(float2);
+  OF_CK(c, hipMemcpyAsync(o, hdr, sizeof(hdr), hipMemcpyHostToDevice, c->st));
+  o += align_up(sizeof(hdr));
+  OF_CK(c, hipMemcpyAsync(o, c->d.scal, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(sizeof(DevScalars));
+  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par], 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par ^ 1], 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(o, c->d.wbuf[par], vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(o, c->d.cbuf[par], vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(o, c->d.b, vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(o, c->d.H, L.ntiles * kTile * kTile * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+  OF_CK(c, hipStreamSynchronize(c->st));  // the header came from host stack memory
+  return OFISTA_OK;
+}
+
+ofista_status ofista_import_state(ofista_ctx *c, const void *d_buf) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_buf) return OFISTA_E_ARG;
+  const Layout &L = c->L;
+  double hdr[16];
+  const char *o = static_cast<const char *>(d_buf);
+  OF_CK(c, hipStreamSynchronize(c->st));
+  OF_CK(c, hipMemcpy(hdr, o, sizeof(hdr), hipMemcpyDeviceToHost));
+  if (hdr[4] != static_cast<double>(L.N) || hdr[5] != static_cast<double>(L.K)) return OFISTA_E_ARG;
+  c->n = static_cast<int64_t>(hdr[0]);
+  c->G = static_cast<int64_t>(hdr[1]);
+  c->t = hdr[2];
+  c->have_iter = hdr[3] != 0.0;
+  const int par = static_cast<int>(c->G & 1);
+  const size_t vec = static_cast<size_t>(L.Npad) * sizeof(float2);
+  o += align_up(sizeof(hdr));
+  OF_CK(c, hipMemcpyAsync(c->d.scal, o, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(sizeof(DevScalars));
+  OF_CK(c, hipMemcpyAsync(c->d.slots[par], o, 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(c->d.slots[par ^ 1], o, 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(c->d.wbuf[par], o, vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(c->d.cbuf[par], o, vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(c->d.b, o, vec, hipMemcpyDeviceToDevice, c->st));
+  o += align_up(vec);
+  OF_CK(c, hipMemcpyAsync(c->d.H, o, L.ntiles * kTile * kTile * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+  OF_CK(c, launch_fill(c->d.cnt, L.nb, 0u, c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_profile(ofista_ctx *c, int32_t enable) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  OF_CK(c, hipStreamSynchronize(c->st));
+  for (auto &p : c->ev) {
+    c->pool.push_back(p.second.first);
+    c->pool.push_back(p.second.second);
+  }
+  c->ev.clear();
+  c->prof = enable != 0;
+  return OFISTA_OK;
+}
+
+ofista_status ofista_kernel_time(ofista_ctx *c, int32_t kernel, double *total_ms, int64_t *launches) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!total_ms || !launches || kernel < 0 || kernel >= kProfN) return OFISTA_E_ARG;
+  OF_CK(c, hipStreamSynchronize(c->st));
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto &p : c->ev) {
+    if (p.first != kernel) continue;
+    float ms = 0.f;
+    OF_CK(c, hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return OFISTA_OK;
+}
+
+void ofista_destroy(ofista_ctx *c) {
+  if (!c) return;
+  for (auto &p : c->ev) {
+    hipEventDestroy(p.second.first);
+    hipEventDestroy(p.second.second);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  delete c;
+}
+
+const char *ofista_error_string(const ofista_ctx *c, ofista_status st) {
+  if (c && !c->msg.empty() && st == OFISTA_E_HIP) return c->msg.c_str();
+  return status_text(st);
+}
+
+}  // extern "C"

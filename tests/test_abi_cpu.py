@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, sizes workspaces consistently and rejects bad arguments with the
+documented status codes before touching the device."""
+
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "ofista.h"
+LIB = ROOT / "paper_2603_08582_amd" / "libofista.so"
+
+pytestmark = pytest.mark.skipif(not LIB.exists(), reason="libofista.so not built")
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ofista_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_2603_08582_amd import ofista
+    L = ofista.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def small_cfg(**kw):
+    from paper_2603_08582_amd import ofista
+    from workload import library_kwargs, make_workload
+    wl = make_workload("small")
+    args = library_kwargs(wl)
+    args.update(kw)
+    return ofista.make_config(**args)
+
+
+def test_workspace_size_covers_packed_gram():
+    from paper_2603_08582_amd import ofista
+    cfg, keep = small_cfg()
+    nbytes = ofista.workspace_bytes(cfg)
+    nb = 1024 // 64
+    packed = nb * (nb + 1) // 2 * 64 * 64 * 8
+    assert nbytes >= packed + 64 * 1024 * 8
+    assert nbytes % 256 == 0 or nbytes > 0
+    assert ofista.lib().ofista_tile() == 64
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n_x", 0, -1), ("n_freq", 0, -1), ("n_freq", 4096, -1), ("dict", 7, -1),
+    ("precision", 9, -1), ("lipschitz", 5, -1), ("momentum", 4, -1), ("lambda_", -1.0, -1),
+    ("record_every", -2, -1),
+])
+def test_bad_config_rejected(field, value, status):
+    from paper_2603_08582_amd import ofista
+    cfg, keep = small_cfg()
+    setattr(cfg, field, value)
+    assert ofista.check_config(cfg) == status
+    assert ofista.workspace_bytes(cfg) == 0
+
+
+def test_haar_constraints():
+    from paper_2603_08582_amd import ofista
+    cfg, keep = small_cfg(dictionary="haar", haar_levels=3)
+    assert ofista.check_config(cfg) == 0
+    cfg.haar_levels = 6  # 32 not divisible by 64
+    assert ofista.check_config(cfg) == -1
+    cfg2, keep2 = small_cfg(dictionary="haar", haar_levels=1, n_x=128, n_y=128)
+    assert ofista.check_config(cfg2) == -5  # N > 8192 unsupported for Haar
+
+
+def test_create_rejects_missing_workspace_without_gpu():
+    from paper_2603_08582_amd import ofista
+    L = ofista.lib()
+    cfg, keep = small_cfg()
+    out = ctypes.c_void_p()
+    st = L.ofista_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(out))
+    assert st == -4 and not out.value
+    # misaligned pointer is rejected before any device access
+    st = L.ofista_create(ctypes.byref(cfg), ctypes.c_void_p(0x1001), 1 << 40, None, ctypes.byref(out))
+    assert st == -4
+    assert L.ofista_create(ctypes.byref(cfg), None, 0, None, None) == -1
+
+
+def test_null_ctx_and_error_strings():
+    from paper_2603_08582_amd import ofista
+    L = ofista.lib()
+    assert L.ofista_reset(None) == -1
+    assert L.ofista_push_pulse(None, None, 0, 0.0) == -1
+    assert L.ofista_reconstruct(None, 1, None) == -1
+    L.ofista_destroy(None)
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert L.ofista_error_string(None, st)
+    assert L.ofista_workspace_bytes(None) == 0
+
+
+def test_state_bytes_grows_with_problem():
+    from paper_2603_08582_amd import ofista
+    L = ofista.lib()
+    a, ka = small_cfg()
+    b, kb = small_cfg(n_x=64, n_y=64)
+    sa = L.ofista_state_bytes(ctypes.byref(a))
+    sb = L.ofista_state_bytes(ctypes.byref(b))
+    assert 0 < sa < sb
+    assert sb >= (64 * 64 // 64) * (64 * 64 // 64 + 1) // 2 * 64 * 64 * 8
