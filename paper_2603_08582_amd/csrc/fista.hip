@@ -9,15 +9,21 @@
 // the memory-bound kernel of the path: every element of the upper triangle is
 // read exactly once per step (8 bytes for 16 FP32 FMAs).
 //
-// Work item = tile row I and a run of up to kChunk tiles J0..J1-1.  Wave w of
+// Work item = tile row I and a run of up to 4 or 8 tiles J0..J1-1.  Wave w of
 // the 256-thread workgroup owns rows 16w..16w+15 of each tile and lane l owns
 // column l, so row partial sums stay in registers across the run and are
 // reduced across lanes once per item; column partials are reduced across the
-// 4 waves per tile through LDS.  Every partial lands in its own slot
+// 4 waves through LDS.  Every partial lands in its own slot
 // Q[target row][source] -- no floating-point atomics, so the result is
-// bitwise deterministic.  The workgroup that delivers the last partial of a
-// tile row (arrival counter) sums that row's slots in fixed order and applies
-// the shrink/momentum/power update for those 64 rows.
+// bitwise deterministic.
+//
+// A step is two launches: the tile pass (k_step_tiles) writes the slots, and
+// k_step_update (one workgroup per tile row) sums each row's slots in fixed
+// order and applies the shrink / momentum / power update.  Stream order makes
+// the slots visible to the update.  (Fusing the update into the tile pass with
+// an arrival counter needs every workgroup to wait for its slot stores and the
+// counter round trip before it can retire; on gfx950 that idle time doubled
+// the step even with coherent stores instead of cache-wide fences.)
 #include "ofista_internal.h"
 
 namespace ofista {
@@ -43,26 +49,57 @@ __device__ __forceinline__ float2 cmac_conj(float2 acc, float2 a, float2 x) {
 
 constexpr int kRowsPerWave = kTile / 4;  // 16
 
-// Last-arrival epilogue for tile row R: sum the slots, update 64 rows.
-__device__ void row_epilogue(const StepArgs &a, int R, float4 *red4, double *redd) {
+// Fixed-order tree sum of one double per thread over the 256-thread block.
+__device__ double block_sum256(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+constexpr int kSlotBatch = 8;  // independent slot loads in flight per thread
+
+// Update of tile row R = blockIdx.x: sum the slots, update 64 rows.
+__global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
+  __shared__ float4 red4[256];
+  __shared__ double redd[256];
+  const int R = blockIdx.x;
   const int nb = a.nb;
   const int t = threadIdx.x;
   const int r = t & 63, part = t >> 6;
   // slots written this step for row R: columns j < R (column partials) and the
-  // run starts j = R, R + kChunk, ... (row partials)
+  // run starts j = R, R + chunk, ... (row partials).  Part p adds the slots
+  // j = p, p+4, p+8, ... in increasing j; loads are issued kSlotBatch at a
+  // time (j clamped in range, unused slots replaced by zero after the load).
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const float4 *q = a.Q + static_cast<size_t>(R) * nb * kTile + r;
-  for (int j = part; j < nb; j += 4) {
-    if (j < R || ((j - R) % kChunk) == 0) {
-      const float4 v = q[static_cast<size_t>(j) * kTile];
-      acc.x += v.x;
-      acc.y += v.y;
-      acc.z += v.z;
-      acc.w += v.w;
+  for (int j0 = part; j0 < nb; j0 += 4 * kSlotBatch) {
+    float4 v[kSlotBatch];
+#pragma unroll
+    for (int u = 0; u < kSlotBatch; ++u) {
+      const int j = j0 + 4 * u;
+      v[u] = q[static_cast<size_t>(j < nb ? j : nb - 1) * kTile];
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotBatch; ++u) {
+      const int j = j0 + 4 * u;
+      const bool ok = j < nb && (j < R || ((j - R) % a.chunk) == 0);
+      acc.x += ok ? v[u].x : 0.f;
+      acc.y += ok ? v[u].y : 0.f;
+      acc.z += ok ? v[u].z : 0.f;
+      acc.w += ok ? v[u].w : 0.f;
     }
   }
   red4[t] = acc;
-  __syncthreads();
+  // |w|^2 of the vector this step multiplied: fixed-order tree over the slots
+  double m = 0.0;
+  for (int j = t; j < nb; j += 256) m += a.slot_prev[nb + j];
+  const double wn2 = block_sum256(m, redd);  // also orders red4 before its use
   if (t < 64) {
     float4 s = red4[t];
 #pragma unroll
@@ -73,9 +110,6 @@ __device__ void row_epilogue(const StepArgs &a, int R, float4 *red4, double *red
       s.z += v.z;
       s.w += v.w;
     }
-    // |w|^2 of the vector this step multiplied (fixed-order sum of the slots)
-    double wn2 = 0.0;
-    for (int j = 0; j < nb; ++j) wn2 += a.slot_prev[nb + j];
     const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
     const float tau = static_cast<float>(a.scal->tau);
     const float alpha = static_cast<float>(a.scal->alpha);
@@ -118,17 +152,12 @@ __device__ void row_epilogue(const StepArgs &a, int R, float4 *red4, double *red
     }
     a.slot_cur[R] = rs;
     a.slot_cur[nb + R] = ms;
-    a.cnt[R] = 0u;  // ready for the next step
   }
-  __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_fista_step(StepArgs a) {
-  __shared__ float4 colbuf[4][64];
-  __shared__ float4 red4[256];
-  __shared__ double redd[128];
-  __shared__ int last_list[kChunk + 1];
-  __shared__ int n_last;
+template <int CH>
+__global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
+  __shared__ float4 colbuf[CH][4][64];
 
   const WorkItem it = a.items[blockIdx.x];
   const int I = it.I, J0 = it.J0, J1 = it.J1;
@@ -151,14 +180,25 @@ __global__ __launch_bounds__(256) void k_fista_step(StepArgs a) {
   }
 
   const int trow = a.tile_row0[I];
+  const float2 *Hrow = a.H + static_cast<size_t>(trow - I) * (kTile * kTile) + row0 * kTile + lane;
+  // tile J lives at Hrow + J * kTile * kTile; the next tile's rows are loaded
+  // while the current one is multiplied
+  float2 hn[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) hn[q] = Hrow[static_cast<size_t>(J0) * kTile * kTile + q * kTile];
+  float2 zn = a.zc[J0 * kTile + lane], wn = a.wc[J0 * kTile + lane];
   for (int J = J0; J < J1; ++J) {
-    const float2 *Ht = a.H + static_cast<size_t>(trow + (J - I)) * (kTile * kTile) +
-                       row0 * kTile + lane;
     float2 h[kRowsPerWave];
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) h[q] = Ht[q * kTile];
-    const float2 zj = a.zc[J * kTile + lane];
-    const float2 wj = a.wc[J * kTile + lane];
+    for (int q = 0; q < kRowsPerWave; ++q) h[q] = hn[q];
+    const float2 zj = zn, wj = wn;
+    if (J + 1 < J1) {
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q)
+        hn[q] = Hrow[static_cast<size_t>(J + 1) * kTile * kTile + q * kTile];
+      zn = a.zc[(J + 1) * kTile + lane];
+      wn = a.wc[(J + 1) * kTile + lane];
+    }
     float2 cz = make_float2(0.f, 0.f), cw = make_float2(0.f, 0.f);
 #pragma unroll
     for (int q = 0; q < kRowsPerWave; ++q) {
@@ -167,23 +207,7 @@ __global__ __launch_bounds__(256) void k_fista_step(StepArgs a) {
       cz = cmac_conj(cz, h[q], zI[q]);
       cw = cmac_conj(cw, h[q], wI[q]);
     }
-    if (J != I) {
-      colbuf[wave][lane] = make_float4(cz.x, cz.y, cw.x, cw.y);
-      __syncthreads();
-      if (wave == 0) {
-        float4 s = colbuf[0][lane];
-#pragma unroll
-        for (int w = 1; w < 4; ++w) {
-          const float4 v = colbuf[w][lane];
-          s.x += v.x;
-          s.y += v.y;
-          s.z += v.z;
-          s.w += v.w;
-        }
-        a.Q[(static_cast<size_t>(J) * a.nb + I) * kTile + lane] = s;
-      }
-      __syncthreads();
-    }
+    colbuf[J - J0][wave][lane] = make_float4(cz.x, cz.y, cw.x, cw.y);
   }
 
   // Row partials: 16 rows x (yz, yw) = 64 floats per lane, summed over the 64
@@ -207,52 +231,53 @@ __global__ __launch_bounds__(256) void k_fista_step(StepArgs a) {
       v[e] = keep + __shfl_xor(send, half);
     }
   }
-  {
-    float *dst = reinterpret_cast<float *>(a.Q + (static_cast<size_t>(I) * a.nb + J0) * kTile + row0);
-    dst[lane] = v[0];
+  reinterpret_cast<float *>(a.Q + (static_cast<size_t>(I) * a.nb + J0) * kTile + row0)[lane] = v[0];
+
+  // Column partials of the off-diagonal tiles: sum the 4 waves in fixed order.
+  __syncthreads();
+#pragma unroll
+  for (int jj = threadIdx.x >> 6; jj < CH; jj += 4) {
+    const int J = J0 + jj;
+    if (J < J1 && J != I) {
+      float4 s = colbuf[jj][0][lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const float4 t = colbuf[jj][w][lane];
+        s.x += t.x;
+        s.y += t.y;
+        s.z += t.z;
+        s.w += t.w;
+      }
+      a.Q[(static_cast<size_t>(J) * a.nb + I) * kTile + lane] = s;
+    }
   }
 
-  // publish, then count arrivals for every tile row this item fed
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int n = 0;
-    unsigned old = atomicAdd(&a.cnt[I], 1u);
-    if (old + 1u == a.expect[I]) last_list[n++] = I;
-    for (int J = J0; J < J1; ++J) {
-      if (J == I) continue;
-      old = atomicAdd(&a.cnt[J], 1u);
-      if (old + 1u == a.expect[J]) last_list[n++] = J;
-    }
-    n_last = n;
-  }
-  __syncthreads();
-  const int nl = n_last;
-  if (nl > 0) {
-    __threadfence();
-    for (int k = 0; k < nl; ++k) row_epilogue(a, last_list[k], red4, redd);
-  }
 }
 
 // Per-pulse scalars: lambda (first pulse), sigma^2 of position s, rho_{n-1}
-// from the power-vector slots, L_n, tau, alpha.  One thread.
-__global__ void k_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
-                          double lam_in, int lip, int have_rho, const double *slot_r,
-                          const double *slot_m, int nb) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// from the power-vector slots, L_n, tau, alpha.  One 256-thread workgroup;
+// the slot sums use the same fixed-order tree as the step epilogue.
+__global__ __launch_bounds__(256) void k_scalars(DevScalars *scal, const double *sig2, int s,
+                                                 int first, int rel, double lam_in, int lip,
+                                                 int have_rho, const double *slot_r,
+                                                 const double *slot_m, int nb) {
+  __shared__ double red[256];
+  double rho = 0.0;
+  if (have_rho) {
+    double pr = 0.0, pm = 0.0;
+    for (int j = threadIdx.x; j < nb; j += 256) {
+      pr += slot_r[j];
+      pm += slot_m[nb + j];
+    }
+    const double rs = block_sum256(pr, red);
+    const double ms = block_sum256(pm, red);
+    rho = rs / ms;
+  }
+  if (threadIdx.x != 0) return;
   if (first) {
     scal->lam = rel ? lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : lam_in;
   }
   const double sigma2 = sig2[s];
-  double rho = 0.0;
-  if (have_rho) {
-    double rs = 0.0, ms = 0.0;
-    for (int j = 0; j < nb; ++j) {
-      rs += slot_r[j];
-      ms += slot_m[nb + j];
-    }
-    rho = rs / ms;
-  }
   const double L = lip == 0 ? rho + sigma2 : scal->L + sigma2;
   scal->sigma2 = sigma2;
   scal->rho = rho;
@@ -279,15 +304,25 @@ __global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int
 
 }  // namespace
 
-hipError_t launch_fista_step(const StepArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_fista_step, dim3(a.nitems), dim3(256), 0, st, a);
+hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st) {
+  if (a.chunk == 8)
+    hipLaunchKernelGGL(k_step_tiles<8>, dim3(a.nitems), dim3(256), 0, st, a);
+  else if (a.chunk == 4)
+    hipLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_step_update(const StepArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_update, dim3(a.nb), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
                           double lam_in, int lip, int have_rho, const double *slot_r,
                           const double *slot_m, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(64), 0, st, scal, sig2, s, first, rel, lam_in,
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, st, scal, sig2, s, first, rel, lam_in,
                      lip, have_rho, slot_r, slot_m, nb);
   return hipGetLastError();
 }

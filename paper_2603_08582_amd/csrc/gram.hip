@@ -17,60 +17,79 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// b += A^H (d e^{-i phi}); optional block max of |Delta b| for lambda.
+constexpr int kCorrPix = 64;    // pixels per workgroup
+constexpr int kCorrGroups = 4;  // frequency groups per workgroup (k = g, g+4, ...)
+
+// b += A^H (d e^{-i phi}); at the first pulse also max_i |Delta b_i| for
+// lambda.  Workgroup = 64 pixels x 4 frequency groups; the 4 group sums are
+// added in fixed order.
 __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__ A,
                                               const float2 *__restrict__ d,
                                               float cphi, float sphi,
                                               float2 *__restrict__ b,
                                               DevScalars *__restrict__ scal, int first) {
   extern __shared__ float2 dl[];  // K rotated samples
-  __shared__ float red[256];
+  __shared__ float2 part[kCorrGroups][kCorrPix];
+  __shared__ float red[kCorrPix];
   for (int k = threadIdx.x; k < g.K; k += 256) {
     const float2 v = d[k];
     // d e^{-i phi} = (v.x + i v.y)(cos phi - i sin phi)
     dl[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  float mag = 0.f;
-  if (i < g.Npad) {
-    float re = 0.f, im = 0.f;
-    const float2 *col = A + i;
-    for (int k = 0; k < g.K; ++k) {
-      const float2 a = col[static_cast<size_t>(k) * g.Npad];
-      const float2 x = dl[k];
-      // conj(a) * x
-      re += a.x * x.x + a.y * x.y;
-      im += a.x * x.y - a.y * x.x;
+  const int px = threadIdx.x & (kCorrPix - 1);
+  const int grp = threadIdx.x / kCorrPix;
+  const int i = blockIdx.x * kCorrPix + px;  // < Npad (Npad is a multiple of 64)
+  float re = 0.f, im = 0.f;
+  for (int k = grp; k < g.K; k += kCorrGroups) {
+    const float2 a = A[static_cast<size_t>(k) * g.Npad + i];
+    const float2 x = dl[k];
+    // conj(a) * x
+    re += a.x * x.x + a.y * x.y;
+    im += a.x * x.y - a.y * x.x;
+  }
+  part[grp][px] = make_float2(re, im);
+  __syncthreads();
+  if (grp == 0) {
+    float2 s = part[0][px];
+#pragma unroll
+    for (int q = 1; q < kCorrGroups; ++q) {
+      s.x += part[q][px].x;
+      s.y += part[q][px].y;
     }
     float2 bi = b[i];
-    bi.x += re;
-    bi.y += im;
+    bi.x += s.x;
+    bi.y += s.y;
     b[i] = bi;
-    mag = sqrtf(re * re + im * im);
+    red[px] = sqrtf(s.x * s.x + s.y * s.y);
   }
   if (first) {
-    red[threadIdx.x] = mag;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int q = 0; q < kCorrPix; ++q) m = fmaxf(m, red[q]);
+      // max of non-negative floats: integer order equals float order
+      atomicMax(&scal->dbmax_bits, __float_as_uint(m));
     }
-    // max of non-negative floats: integer order equals float order
-    if (threadIdx.x == 0) atomicMax(&scal->dbmax_bits, __float_as_uint(red[0]));
   }
 }
 
 // H(I, J) += A_I^H A_J for one 64 x 64 tile per workgroup, 4 waves each
-// owning a 32 x 32 quadrant.  Workgroup b runs on XCD b % 8; logical tile
-// (b % 8) * per + b / 8 keeps runs of neighbouring tiles (shared A blocks) on
-// one XCD's L2.
+// owning a 32 x 32 quadrant; KB frequencies are staged through LDS per step,
+// the next step's operands are loaded into registers while the matrix cores
+// work on the current one.  Workgroup b runs on XCD b % 8; logical tile
+// (b % 8) * per + b / 8 gives each XCD a contiguous run of the tile table,
+// whose order (8 x 8 super-tiles) keeps the A blocks of concurrently running
+// tiles inside one XCD's L2.
+template <int KB>
 __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_grid,
                                                    const float2 *__restrict__ A,
                                                    const int2 *__restrict__ tile_ij,
                                                    float2 *__restrict__ H) {
-  __shared__ float2 sa[kGramKB][kTile];
-  __shared__ float2 sb[kGramKB][kTile];
+  static_assert(KB % 8 == 0, "two float4 loads per thread per 8 frequencies");
+  constexpr int kLoads = KB / 8;  // float4 per thread per operand and step
+  __shared__ float2 sa[KB][kTile];
+  __shared__ float2 sb[KB][kTile];
   const int per = ntiles_grid >> 3;
   const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int2 ij = tile_ij[logical];
@@ -88,43 +107,41 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
     accI[r] = 0.f;
   }
 
-  // staging: kGramKB x 64 complex per operand = 512 float4; 2 per thread
+  // staging: KB x 64 complex per operand = KB*32 float4; element r of a
+  // thread's prefetch is frequency (threadIdx.x + 256 r) / 32 of the step,
+  // float4 column (threadIdx.x + 256 r) % 32
   const float4 *Ag = reinterpret_cast<const float4 *>(A);
   const int rowf4 = Npad >> 1;  // float4 per A row
-  float4 pa[2], pb[2];
-  auto gload = [&](int k0) {
+  const int kk0 = threadIdx.x >> 5, c2 = threadIdx.x & 31;
+  const float4 *pI = Ag + I * (kTile / 2) + c2;
+  const float4 *pJ = Ag + J * (kTile / 2) + c2;
+  float4 pa[kLoads], pb[kLoads];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = threadIdx.x + r * 256;
-      const int kk = idx >> 5, c2 = idx & 31;
-      const int k = k0 + kk;
-      if (k < K) {
-        pa[r] = Ag[static_cast<size_t>(k) * rowf4 + I * (kTile / 2) + c2];
-        pb[r] = Ag[static_cast<size_t>(k) * rowf4 + J * (kTile / 2) + c2];
-      } else {
-        pa[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-        pb[r] = pa[r];
+  for (int r = 0; r < kLoads; ++r) {
+    const int k = kk0 + 8 * r;
+    const bool in = k < K;
+    pa[r] = in ? pI[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    pb[r] = in ? pJ[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int r = 0; r < kLoads; ++r) {
+    reinterpret_cast<float4 *>(&sa[kk0 + 8 * r][0])[c2] = pa[r];
+    reinterpret_cast<float4 *>(&sb[kk0 + 8 * r][0])[c2] = pb[r];
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += KB) {
+    const bool more = k0 + KB < K;
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < kLoads; ++r) {
+        const int k = k0 + KB + kk0 + 8 * r;
+        const bool in = k < K;
+        pa[r] = in ? pI[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        pb[r] = in ? pJ[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
-  };
-  auto lstore = [&]() {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = threadIdx.x + r * 256;
-      const int kk = idx >> 5, c2 = idx & 31;
-      reinterpret_cast<float4 *>(&sa[kk][0])[c2] = pa[r];
-      reinterpret_cast<float4 *>(&sb[kk][0])[c2] = pb[r];
-    }
-  };
-
-  gload(0);
-  lstore();
-  __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += kGramKB) {
-    const bool more = k0 + kGramKB < K;
-    if (more) gload(k0 + kGramKB);
-#pragma unroll
-    for (int kk = 0; kk < kGramKB; ++kk) {
+    for (int kk = 0; kk < KB; ++kk) {
       const float2 a = sa[kk][wi * 32 + li];
       const float2 c = sb[kk][wj * 32 + li];
       const float av = hi ? a.y : a.x;
@@ -135,28 +152,34 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
     }
     __syncthreads();
     if (more) {
-      lstore();
+#pragma unroll
+      for (int r = 0; r < kLoads; ++r) {
+        reinterpret_cast<float4 *>(&sa[kk0 + 8 * r][0])[c2] = pa[r];
+        reinterpret_cast<float4 *>(&sb[kk0 + 8 * r][0])[c2] = pb[r];
+      }
       __syncthreads();
     }
   }
 
   // epilogue: read-modify-write of the packed tile.  Accumulator register r of
   // lane l holds row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the quadrant.
-  size_t tile_index;
-  {
-    const int nb = Npad / kTile;
-    tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
-  }
+  const int nb = Npad / kTile;
+  const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
   float2 *Ht = H + tile_index * (kTile * kTile);
+  float2 h[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    h[r] = Ht[row * kTile + wj * 32 + li];
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     const int col = wj * 32 + li;
-    float2 h = Ht[row * kTile + col];
-    h.x += accR[r];
-    h.y += accI[r];
-    if (I == J && row == col) h.y = 0.f;
-    Ht[row * kTile + col] = h;
+    h[r].x += accR[r];
+    h[r].y += accI[r];
+    if (I == J && row == col) h[r].y = 0.f;
+    Ht[row * kTile + col] = h[r];
   }
 }
 
@@ -184,7 +207,7 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
                        double cos_c, double sin_c, float2 *b, DevScalars *scal,
                        int first, hipStream_t st) {
   const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
-  hipLaunchKernelGGL(k_corr, dim3((g.Npad + 255) / 256), dim3(256), lds, st, g, A, d,
+  hipLaunchKernelGGL(k_corr, dim3(g.Npad / kCorrPix), dim3(256), lds, st, g, A, d,
                      static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first);
   return hipGetLastError();
 }
@@ -192,7 +215,7 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_fp32, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
+  hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
                      ntiles_grid, A, tile_ij, H);
   return hipGetLastError();
 }

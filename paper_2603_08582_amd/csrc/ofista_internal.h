@@ -13,10 +13,11 @@ namespace ofista {
 // the nb(nb+1)/2 tiles (I, J), I <= J, of a zero-padded Npad x Npad matrix
 // (Npad = nb * kTile), each tile row-major, tiles in row-major upper order.
 constexpr int kTile = 64;
-// Tiles per FISTA work item (a run of tiles along one tile row).
-constexpr int kChunk = 4;
+// Tiles per FISTA work item (a run of tiles along one tile row): 4 or 8.
+constexpr int kChunkSmall = 4;
+constexpr int kChunkLarge = 8;
 // Frequencies staged per LDS step of the Gram update.
-constexpr int kGramKB = 16;
+constexpr int kGramKB = 32;
 
 constexpr double kC0 = 299792458.0;  // speed of light, m/s
 constexpr double kPi = 3.141592653589793238462643383279502884;
@@ -55,8 +56,6 @@ struct DevState {
   float2 *zbuf[2];   // momentum point z
   float2 *wbuf[2];   // power vector
   float4 *Q;         // matvec partials, nb x nb x kTile of (yz, yw)
-  unsigned *cnt;     // arrival counters per tile row (kept at 0 between launches)
-  unsigned *expect;  // arrivals per tile row per FISTA step
   double *slots[2];  // per tile row: [0, nb) Re<w, Hw> parts, [nb, 2nb) |w'|^2 parts
   DevScalars *scal;
   double *pos;       // npos x 3
@@ -105,17 +104,16 @@ struct StepArgs {
   float2 *zn;
   float2 *wn;
   float4 *Q;
-  unsigned *cnt;
-  const unsigned *expect;
   const double *slot_prev;
   double *slot_cur;
   const DevScalars *scal;
   const WorkItem *items;
   const int *tile_row0;
-  int nb, N, nitems;
+  int nb, N, nitems, chunk;
   float beta;
 };
-hipError_t launch_fista_step(const StepArgs &a, hipStream_t st);
+hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st);
+hipError_t launch_step_update(const StepArgs &a, hipStream_t st);
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
                           int first, int rel, double lam_in, int lip,
                           int have_rho, const double *slot_r,

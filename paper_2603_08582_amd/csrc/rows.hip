@@ -69,26 +69,30 @@ __device__ void haar_level_analysis(float2 *buf, int n, int m) {
   const int h = m >> 1;
   const int nblk = h * h;
   float2 o[kMaxPer][4];
-  int cnt = 0;
-  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q >= nblk) break;
     const int y = q / h, x = q % h;
     const float2 a = buf[(2 * y) * n + 2 * x];
     const float2 b = buf[(2 * y) * n + 2 * x + 1];
     const float2 c = buf[(2 * y + 1) * n + 2 * x];
     const float2 d = buf[(2 * y + 1) * n + 2 * x + 1];
-    o[cnt][0] = make_float2(0.5f * ((a.x + b.x) + (c.x + d.x)), 0.5f * ((a.y + b.y) + (c.y + d.y)));
-    o[cnt][1] = make_float2(0.5f * ((a.x - b.x) + (c.x - d.x)), 0.5f * ((a.y - b.y) + (c.y - d.y)));
-    o[cnt][2] = make_float2(0.5f * ((a.x + b.x) - (c.x + d.x)), 0.5f * ((a.y + b.y) - (c.y + d.y)));
-    o[cnt][3] = make_float2(0.5f * ((a.x - b.x) - (c.x - d.x)), 0.5f * ((a.y - b.y) - (c.y - d.y)));
+    o[u][0] = make_float2(0.5f * ((a.x + b.x) + (c.x + d.x)), 0.5f * ((a.y + b.y) + (c.y + d.y)));
+    o[u][1] = make_float2(0.5f * ((a.x - b.x) + (c.x - d.x)), 0.5f * ((a.y - b.y) + (c.y - d.y)));
+    o[u][2] = make_float2(0.5f * ((a.x + b.x) - (c.x + d.x)), 0.5f * ((a.y + b.y) - (c.y + d.y)));
+    o[u][3] = make_float2(0.5f * ((a.x - b.x) - (c.x - d.x)), 0.5f * ((a.y - b.y) - (c.y - d.y)));
   }
   __syncthreads();
-  cnt = 0;
-  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q >= nblk) break;
     const int y = q / h, x = q % h;
-    buf[y * n + x] = o[cnt][0];
-    buf[y * n + x + h] = o[cnt][1];
-    buf[(y + h) * n + x] = o[cnt][2];
-    buf[(y + h) * n + x + h] = o[cnt][3];
+    buf[y * n + x] = o[u][0];
+    buf[y * n + x + h] = o[u][1];
+    buf[(y + h) * n + x] = o[u][2];
+    buf[(y + h) * n + x + h] = o[u][3];
   }
   __syncthreads();
 }
@@ -99,26 +103,30 @@ __device__ void haar_level_synthesis(float2 *buf, int n, int m) {
   const int h = m >> 1;
   const int nblk = h * h;
   float2 o[kMaxPer][4];
-  int cnt = 0;
-  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q >= nblk) break;
     const int y = q / h, x = q % h;
     const float2 ll = buf[y * n + x];
     const float2 tr = buf[y * n + x + h];
     const float2 bl = buf[(y + h) * n + x];
     const float2 hh = buf[(y + h) * n + x + h];
-    o[cnt][0] = make_float2(0.5f * ((ll.x + tr.x) + (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) + (bl.y + hh.y)));
-    o[cnt][1] = make_float2(0.5f * ((ll.x - tr.x) + (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) + (bl.y - hh.y)));
-    o[cnt][2] = make_float2(0.5f * ((ll.x + tr.x) - (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) - (bl.y + hh.y)));
-    o[cnt][3] = make_float2(0.5f * ((ll.x - tr.x) - (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) - (bl.y - hh.y)));
+    o[u][0] = make_float2(0.5f * ((ll.x + tr.x) + (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) + (bl.y + hh.y)));
+    o[u][1] = make_float2(0.5f * ((ll.x - tr.x) + (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) + (bl.y - hh.y)));
+    o[u][2] = make_float2(0.5f * ((ll.x + tr.x) - (bl.x + hh.x)), 0.5f * ((ll.y + tr.y) - (bl.y + hh.y)));
+    o[u][3] = make_float2(0.5f * ((ll.x - tr.x) - (bl.x - hh.x)), 0.5f * ((ll.y - tr.y) - (bl.y - hh.y)));
   }
   __syncthreads();
-  cnt = 0;
-  for (int q = threadIdx.x; q < nblk; q += blockDim.x, ++cnt) {
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q >= nblk) break;
     const int y = q / h, x = q % h;
-    buf[(2 * y) * n + 2 * x] = o[cnt][0];
-    buf[(2 * y) * n + 2 * x + 1] = o[cnt][1];
-    buf[(2 * y + 1) * n + 2 * x] = o[cnt][2];
-    buf[(2 * y + 1) * n + 2 * x + 1] = o[cnt][3];
+    buf[(2 * y) * n + 2 * x] = o[u][0];
+    buf[(2 * y) * n + 2 * x + 1] = o[u][1];
+    buf[(2 * y + 1) * n + 2 * x] = o[u][2];
+    buf[(2 * y + 1) * n + 2 * x + 1] = o[u][3];
   }
   __syncthreads();
 }

@@ -21,7 +21,7 @@ DICT = {"identity": 0, "haar": 1}
 PRECISION = {"fp32": 0, "split_bf16": 1}
 LIPSCHITZ = {"running": 0, "bound": 1}
 MOMENTUM = {"fista": 0, "restart": 1, "ista": 2}
-KERNEL = {"gram": 0, "step": 1, "rows": 2, "corr": 3, "scalars": 4}
+KERNEL = {"gram": 0, "step": 1, "rows": 2, "corr": 3, "scalars": 4, "update": 5}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_RANGE", -3: "E_STATE", -4: "E_WORKSPACE",
           -5: "E_UNSUPPORTED", -6: "E_HIP"}
