@@ -175,9 +175,10 @@ ofista_status ofista_import_state(struct ofista_ctx *ctx, const void *d_buf);
 /* Per-kernel timing with HIP events on the ctx's stream.  While enabled, every
    launch of the named kernel class is bracketed by a pair of events.
    ofista_kernel_time synchronises and returns the summed milliseconds and the
-   launch count since enabling.  kernel: 0 Gram update, 1 FISTA-step tile pass
-   (the H z / H w streaming), 2 rows, 3 correlation, 4 scalars, 5 FISTA-step
-   update (slot sums, shrink, momentum, power vector). */
+   launch count since enabling.  kernel: 0 Gram update (with the correlation
+   b += A_s^H d fused in), 1 FISTA-step tile pass (the H z / H w streaming),
+   2 rows, 3 unused, 4 scalars, 5 FISTA-step update (slot sums, shrink,
+   momentum, power vector). */
 ofista_status ofista_profile(struct ofista_ctx *ctx, int32_t enable);
 ofista_status ofista_kernel_time(struct ofista_ctx *ctx, int32_t kernel,
                                  double *total_ms, int64_t *launches);

@@ -1,6 +1,8 @@
 // Sufficient-statistic updates of one pulse (Section III-C):
-//   b += A_s^H d~          (correlation; at the first pulse also max_i |Delta b_i|)
 //   H += A_s^H A_s         (rank-K Hermitian Gram update on the matrix cores)
+//   b += A_s^H d~          (correlation, formed by the diagonal-tile workgroups
+//                           from the A blocks they already stage; at the first
+//                           pulse also max_i |Delta b_i|)
 //
 // The Gram update is the one dense contraction on the path.  For a tile
 // (I, J) of H, with a = A_s[k, I-block] and a' = A_s[k, J-block] complex,
@@ -17,63 +19,6 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kCorrPix = 64;    // pixels per workgroup
-constexpr int kCorrGroups = 4;  // frequency groups per workgroup (k = g, g+4, ...)
-
-// b += A^H (d e^{-i phi}); at the first pulse also max_i |Delta b_i| for
-// lambda.  Workgroup = 64 pixels x 4 frequency groups; the 4 group sums are
-// added in fixed order.
-__global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__ A,
-                                              const float2 *__restrict__ d,
-                                              float cphi, float sphi,
-                                              float2 *__restrict__ b,
-                                              DevScalars *__restrict__ scal, int first) {
-  extern __shared__ float2 dl[];  // K rotated samples
-  __shared__ float2 part[kCorrGroups][kCorrPix];
-  __shared__ float red[kCorrPix];
-  for (int k = threadIdx.x; k < g.K; k += 256) {
-    const float2 v = d[k];
-    // d e^{-i phi} = (v.x + i v.y)(cos phi - i sin phi)
-    dl[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
-  }
-  __syncthreads();
-  const int px = threadIdx.x & (kCorrPix - 1);
-  const int grp = threadIdx.x / kCorrPix;
-  const int i = blockIdx.x * kCorrPix + px;  // < Npad (Npad is a multiple of 64)
-  float re = 0.f, im = 0.f;
-  for (int k = grp; k < g.K; k += kCorrGroups) {
-    const float2 a = A[static_cast<size_t>(k) * g.Npad + i];
-    const float2 x = dl[k];
-    // conj(a) * x
-    re += a.x * x.x + a.y * x.y;
-    im += a.x * x.y - a.y * x.x;
-  }
-  part[grp][px] = make_float2(re, im);
-  __syncthreads();
-  if (grp == 0) {
-    float2 s = part[0][px];
-#pragma unroll
-    for (int q = 1; q < kCorrGroups; ++q) {
-      s.x += part[q][px].x;
-      s.y += part[q][px].y;
-    }
-    float2 bi = b[i];
-    bi.x += s.x;
-    bi.y += s.y;
-    b[i] = bi;
-    red[px] = sqrtf(s.x * s.x + s.y * s.y);
-  }
-  if (first) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float m = 0.f;
-      for (int q = 0; q < kCorrPix; ++q) m = fmaxf(m, red[q]);
-      // max of non-negative floats: integer order equals float order
-      atomicMax(&scal->dbmax_bits, __float_as_uint(m));
-    }
-  }
-}
-
 // H(I, J) += A_I^H A_J for one 64 x 64 tile per workgroup, 4 waves each
 // owning a 32 x 32 quadrant; KB frequencies are staged through LDS per step,
 // the next step's operands are loaded into registers while the matrix cores
@@ -85,11 +30,12 @@ template <int KB>
 __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_grid,
                                                    const float2 *__restrict__ A,
                                                    const int2 *__restrict__ tile_ij,
-                                                   float2 *__restrict__ H) {
+                                                   float2 *__restrict__ H, CorrArgs corr) {
   static_assert(KB % 8 == 0, "two float4 loads per thread per 8 frequencies");
   constexpr int kLoads = KB / 8;  // float4 per thread per operand and step
   __shared__ float2 sa[KB][kTile];
   __shared__ float2 sb[KB][kTile];
+  __shared__ float2 sd[kMaxFreq];  // rotated pulse, diagonal tiles only
   const int per = ntiles_grid >> 3;
   const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int2 ij = tile_ij[logical];
@@ -99,6 +45,18 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
   const int wi = wave >> 1, wj = wave & 1;
   const bool hi = lane >= 32;
   const int li = lane & 31;
+  // Correlation on the diagonal tiles: b_I += A_I^H d~ from the staged A_I.
+  // Thread t sums column t % 64 over frequencies kk in [g KB/4, (g+1) KB/4)
+  // of every stage, g = t / 64; the four groups are added in fixed order.
+  const bool diag = I == J;
+  float2 bacc = make_float2(0.f, 0.f);
+  if (diag) {
+    for (int k = threadIdx.x; k < K; k += 256) {
+      const float2 v = corr.d[k];
+      // d e^{-i phi} = (v.x + i v.y)(cos phi - i sin phi)
+      sd[k] = make_float2(v.x * corr.cphi + v.y * corr.sphi, v.y * corr.cphi - v.x * corr.sphi);
+    }
+  }
 
   floatx16 accR, accI;
 #pragma unroll
@@ -150,6 +108,20 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(av, br, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bi, accI, 0, 0, 0);
     }
+    if (diag) {
+      const int cb = threadIdx.x & 63, g = threadIdx.x >> 6;
+#pragma unroll
+      for (int u = 0; u < KB / 4; ++u) {
+        const int kk = g * (KB / 4) + u;
+        if (k0 + kk < K) {
+          const float2 x = sa[kk][cb];
+          const float2 y = sd[k0 + kk];
+          // conj(x) * y
+          bacc.x += x.x * y.x + x.y * y.y;
+          bacc.y += x.x * y.y - x.y * y.x;
+        }
+      }
+    }
     __syncthreads();
     if (more) {
 #pragma unroll
@@ -158,6 +130,37 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
         reinterpret_cast<float4 *>(&sb[kk0 + 8 * r][0])[c2] = pb[r];
       }
       __syncthreads();
+    }
+  }
+
+  if (diag) {
+    // the staging buffers are free after the last stage's barrier
+    float2 *part = &sa[0][0];  // [4][64]
+    float *mag = reinterpret_cast<float *>(&sb[0][0]);
+    part[threadIdx.x] = bacc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      float2 db = part[threadIdx.x];
+#pragma unroll
+      for (int g = 1; g < 4; ++g) {
+        db.x += part[threadIdx.x + 64 * g].x;
+        db.y += part[threadIdx.x + 64 * g].y;
+      }
+      const int i = I * kTile + threadIdx.x;
+      float2 bi = corr.b[i];
+      bi.x += db.x;
+      bi.y += db.y;
+      corr.b[i] = bi;
+      mag[threadIdx.x] = sqrtf(db.x * db.x + db.y * db.y);
+    }
+    if (corr.first) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float m = 0.f;
+        for (int q = 0; q < 64; ++q) m = fmaxf(m, mag[q]);
+        // max of non-negative floats: integer order equals float order
+        atomicMax(&corr.scal->dbmax_bits, __float_as_uint(m));
+      }
     }
   }
 
@@ -203,20 +206,12 @@ __global__ __launch_bounds__(256) void k_gram_dense(int N, int nb, const float2 
 
 }  // namespace
 
-hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
-                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
-                       int first, hipStream_t st) {
-  const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
-  hipLaunchKernelGGL(k_corr, dim3(g.Npad / kCorrPix), dim3(256), lds, st, g, A, d,
-                     static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first);
-  return hipGetLastError();
-}
-
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
-                            const int2 *tile_ij, int ntiles_grid,
+                            const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
                             hipStream_t st) {
+  if (g.K > kMaxFreq) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
-                     ntiles_grid, A, tile_ij, H);
+                     ntiles_grid, A, tile_ij, H, corr);
   return hipGetLastError();
 }
 

@@ -19,6 +19,9 @@ constexpr int kChunkLarge = 8;
 // Frequencies staged per LDS step of the Gram update.
 constexpr int kGramKB = 32;
 
+// Largest number of frequencies per pulse.
+constexpr int kMaxFreq = 1024;
+
 constexpr double kC0 = 299792458.0;  // speed of light, m/s
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
@@ -83,11 +86,16 @@ hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
                          double *sig2, hipStream_t st);
 
 // ---- gram.hip ----
-hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
-                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
-                       int first, hipStream_t st);
+// Correlation fused into the Gram update: b += A^H (d e^{-i phi}).
+struct CorrArgs {
+  const float2 *d;
+  float cphi, sphi;
+  float2 *b;
+  DevScalars *scal;
+  int first;  // also record max |Delta b| (first pulse)
+};
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
-                            const int2 *tile_ij, int ntiles_grid,
+                            const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
                             hipStream_t st);
 hipError_t launch_gram_dense(const Geom &g, const float2 *H,
                              const int *tile_row0, float2 *out,

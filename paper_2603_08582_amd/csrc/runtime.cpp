@@ -54,7 +54,7 @@ ofista_status check(const ofista_config *c, std::string *why) {
     return bad("grid origin and spacing must be finite");
   if (c->n_pos < 1) return bad("n_pos must be >= 1");
   if (!c->pos_xyz) return bad("pos_xyz is NULL");
-  if (c->n_freq < 1 || c->n_freq > 1024) return bad("n_freq must be in [1, 1024]");
+  if (c->n_freq < 1 || c->n_freq > kMaxFreq) return bad("n_freq must be in [1, 1024]");
   if (!std::isfinite(c->freq0_hz) || !std::isfinite(c->dfreq_hz))
     return bad("frequencies must be finite");
   if (c->dict != OFISTA_DICT_IDENTITY && c->dict != OFISTA_DICT_HAAR2D) return bad("unknown dict");
@@ -396,13 +396,11 @@ ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, d
     OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
   }
   {
-    ProfScope p(c, kProfCorr);
-    OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
-                         std::sin(phase_corr), d.b, d.scal, first, c->st));
-  }
-  {
     ProfScope p(c, kProfGram);
-    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(c->L.ntiles_grid), c->st));
+    CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
+                  static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
+    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(c->L.ntiles_grid), corr,
+                              c->st));
   }
   {
     ProfScope p(c, kProfScalars);

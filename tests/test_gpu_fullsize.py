@@ -1,0 +1,125 @@
+"""Full-size GPU checks at the benchmark workloads' real shapes.
+
+* haar64 (64x64 pixels, Haar(3), K=256, 128 pulses, m=20), run exactly as
+  bench.py runs it, against the oracle's stored result (written by
+  tests/golden/make_golden.py, which calls only the oracle): final image
+  within the FP32 image tolerance 1e-4, every L_n and lambda within 1e-6.
+* large (128x128 pixels, K=512, 256 pulses, m=20): the full oracle run is too
+  slow for a test, so the oracle computes sampled entries one by one --
+  H_n[i, j] and b_n[i] as direct FP64 sums over pulses and frequencies,
+  sigma^2 of sample positions, and lambda from the first pulse.
+"""
+
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from oracle import sar
+from oracle.online_fista import power_sigma2
+from workload import library_kwargs, make_workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_haar64_full_run_matches_stored_oracle():
+    from paper_2603_08582_amd import OnlineFista
+    ref = np.load(GOLDEN / "haar64_oracle.npz")
+    wl = make_workload("haar64")
+    d = sar.echoes(wl).astype(np.complex64)
+    g = OnlineFista(**library_kwargs(wl))
+    dd = torch.from_numpy(d).cuda()
+    Ls, lams = [], []
+    for p in range(wl.spec.n_pulses):
+        g.push_pulse(dd[p], p)
+        st = g.state()
+        Ls.append(st["L"])
+        lams.append(st["lam"])
+        g.reconstruct(wl.spec.inner_steps, copy=False)
+    x = g.image().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(np.array(Ls) / ref["L"] - 1)) < 1e-6
+    assert np.max(np.abs(np.array(lams) / ref["lam"] - 1)) < 1e-6
+    err = rel(x, ref["image"])
+    print(f"haar64 full run: relative image error {err:.3e}")
+    assert err < 1e-4
+    assert abs(g.state()["t"] - float(ref["t"])) < 1e-9 * float(ref["t"])
+
+
+def direct_gram_entry(wl, pix, i, j, pulses):
+    """H_n[i, j] = sum_s sum_k conj(F_s[k, i]) F_s[k, j] in FP64."""
+    f = wl.freqs()
+    tot = 0j
+    for s in range(pulses):
+        F = sar.forward_rows(wl.positions[s], pix[[i, j]], f)
+        tot += np.vdot(F[:, 0], F[:, 1])
+    return tot
+
+
+def direct_b_entry(wl, pix, d, i, pulses):
+    f = wl.freqs()
+    tot = 0j
+    for s in range(pulses):
+        F = sar.forward_rows(wl.positions[s], pix[[i]], f)
+        tot += np.vdot(F[:, 0], d[s])
+    return tot
+
+
+def test_large_full_run_sampled_entries():
+    from paper_2603_08582_amd import OnlineFista
+    wl = make_workload("large")
+    s = wl.spec
+    N, K, P = s.n_pixels, s.n_freq, s.n_pulses
+    d = sar.echoes(wl).astype(np.complex64)
+    g = OnlineFista(**library_kwargs(wl))
+    dd = torch.from_numpy(d).cuda()
+    lam = None
+    for p in range(P):
+        g.push_pulse(dd[p], p)
+        if p == 0:
+            lam = g.state()["lam"]
+        g.reconstruct(s.inner_steps, copy=False)
+    st = g.state()
+    assert st["n_pulses"] == P and st["n_iters"] == P * s.inner_steps
+    pix = wl.pixel_xyz()
+    d64 = d.astype(np.complex128)
+    # lambda from the first pulse
+    F0 = sar.forward_rows(wl.positions[0], pix, wl.freqs())
+    lam_ref = s.lambda_rel * np.max(np.abs(F0.conj().T @ d64[0]))
+    assert abs(lam / lam_ref - 1) < 1e-6
+    # sampled Gram and correlation entries
+    rng = np.random.default_rng(5)
+    ii = rng.integers(0, N, 24)
+    jj = rng.integers(0, N, 24)
+    ii[:4] = jj[:4]  # a few diagonal entries
+    H = g.gram()
+    Hs = H[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].cpu().numpy()
+    del H
+    torch.cuda.empty_cache()
+    scale = P * K
+    for n, (i, j) in enumerate(zip(ii, jj)):
+        ref = direct_gram_entry(wl, pix, int(i), int(j), P)
+        assert abs(Hs[n] - ref) <= 2e-6 * scale, (i, j, Hs[n], ref)
+    b = g.vector("b").cpu().numpy()
+    bscale = np.max(np.abs(b))
+    for i in ii[:12]:
+        ref = direct_b_entry(wl, pix, d64, int(i), P)
+        assert abs(b[i] - ref) <= 2e-6 * bscale
+    # sigma^2 of sample positions, from the state after pushing them again
+    for pos in (0, P // 2, P - 1):
+        F = sar.forward_rows(wl.positions[pos], pix, wl.freqs())
+        ref = power_sigma2(F @ F.conj().T)
+        g.push_pulse(dd[pos], pos)
+        assert abs(g.state()["sigma2"] / ref - 1) < 1e-6
+    x = g.image().cpu().numpy()
+    assert np.all(np.isfinite(x))
+    # the strongest scatterers are found
+    strongest = wl.support[np.argsort(-np.abs(wl.rho[wl.support]))[:20]]
+    top = set(np.argsort(-np.abs(x))[:100].tolist())
+    assert len(top.intersection(strongest.tolist())) >= 15
