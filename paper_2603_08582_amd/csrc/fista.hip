@@ -62,16 +62,39 @@ __device__ double block_sum256(double v, double *red) {
   return r;
 }
 
-constexpr int kSlotBatch = 8;  // independent slot loads in flight per thread
+constexpr int kSlotBatch = 16;  // independent slot loads in flight per thread
 
-// Update of tile row R = blockIdx.x: sum the slots, update 64 rows.
+// Fixed-order sum over a wave (every lane ends with its own, lane 0 with the
+// canonical tree).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Update of tile row R = blockIdx.x: sum the slots, update 64 rows.  All of
+// the workgroup's global loads (row inputs, |w|^2 parts, slots) are issued
+// before any of them is used, so the kernel waits for memory about once.
 __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   __shared__ float4 red4[256];
-  __shared__ double redd[256];
+  __shared__ double wred[4];
   const int R = blockIdx.x;
   const int nb = a.nb;
   const int t = threadIdx.x;
   const int r = t & 63, part = t >> 6;
+  const int i = R * kTile + r;
+  const bool row_thread = t < 64;
+  const bool live = row_thread && i < a.N;
+  float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
+  if (live) {
+    z = a.zc[i];
+    cold = a.cc[i];
+    bi = a.b[i];
+    w = a.wc[i];
+  }
+  // |w|^2 parts of the vector this step multiplied
+  double m = 0.0;
+  for (int j = t; j < nb; j += 256) m += a.slot_prev[nb + j];
   // slots written this step for row R: columns j < R (column partials) and the
   // run starts j = R, R + chunk, ... (row partials).  Part p adds the slots
   // j = p, p+4, p+8, ... in increasing j; loads are issued kSlotBatch at a
@@ -96,11 +119,11 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
     }
   }
   red4[t] = acc;
-  // |w|^2 of the vector this step multiplied: fixed-order tree over the slots
-  double m = 0.0;
-  for (int j = t; j < nb; j += 256) m += a.slot_prev[nb + j];
-  const double wn2 = block_sum256(m, redd);  // also orders red4 before its use
-  if (t < 64) {
+  m = wave_sum(m);
+  if ((t & 63) == 0) wred[t >> 6] = m;
+  __syncthreads();
+  if (row_thread) {
+    const double wn2 = ((wred[0] + wred[1]) + wred[2]) + wred[3];
     float4 s = red4[t];
 #pragma unroll
     for (int p = 1; p < 4; ++p) {
@@ -113,13 +136,8 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
     const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
     const float tau = static_cast<float>(a.scal->tau);
     const float alpha = static_cast<float>(a.scal->alpha);
-    const int i = R * kTile + t;
     double rpart = 0.0, mpart = 0.0;
-    if (i < a.N) {
-      const float2 z = a.zc[i];
-      const float2 cold = a.cc[i];
-      const float2 bi = a.b[i];
-      const float2 w = a.wc[i];
+    if (live) {
       const float gx = s.x - bi.x, gy = s.y - bi.y;
       const float ux = z.x - tau * gx, uy = z.y - tau * gy;
       const float mag = sqrtf(ux * ux + uy * uy);
@@ -140,18 +158,13 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
       a.zn[i] = make_float2(0.f, 0.f);
       a.wn[i] = make_float2(0.f, 0.f);
     }
-    redd[t] = rpart;
-    redd[64 + t] = mpart;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double rs = 0.0, ms = 0.0;
-    for (int k = 0; k < 64; ++k) {
-      rs += redd[k];
-      ms += redd[64 + k];
+    // row-block parts of Re<w, Hw> and |w'|^2, fixed order
+    rpart = wave_sum(rpart);
+    mpart = wave_sum(mpart);
+    if (t == 0) {
+      a.slot_cur[R] = rpart;
+      a.slot_cur[nb + R] = mpart;
     }
-    a.slot_cur[R] = rs;
-    a.slot_cur[nb + R] = ms;
   }
 }
 
@@ -181,24 +194,15 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
 
   const int trow = a.tile_row0[I];
   const float2 *Hrow = a.H + static_cast<size_t>(trow - I) * (kTile * kTile) + row0 * kTile + lane;
-  // tile J lives at Hrow + J * kTile * kTile; the next tile's rows are loaded
-  // while the current one is multiplied
-  float2 hn[kRowsPerWave];
+  float2 hA[kRowsPerWave], hB[kRowsPerWave], zA, wA, zB, wB;
+  auto issue = [&](float2 (&h)[kRowsPerWave], float2 &zz, float2 &ww, int jj) {
+    const int J = min(J0 + jj, J1 - 1);
 #pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) hn[q] = Hrow[static_cast<size_t>(J0) * kTile * kTile + q * kTile];
-  float2 zn = a.zc[J0 * kTile + lane], wn = a.wc[J0 * kTile + lane];
-  for (int J = J0; J < J1; ++J) {
-    float2 h[kRowsPerWave];
-#pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) h[q] = hn[q];
-    const float2 zj = zn, wj = wn;
-    if (J + 1 < J1) {
-#pragma unroll
-      for (int q = 0; q < kRowsPerWave; ++q)
-        hn[q] = Hrow[static_cast<size_t>(J + 1) * kTile * kTile + q * kTile];
-      zn = a.zc[(J + 1) * kTile + lane];
-      wn = a.wc[(J + 1) * kTile + lane];
-    }
+    for (int q = 0; q < kRowsPerWave; ++q) h[q] = Hrow[static_cast<size_t>(J) * kTile * kTile + q * kTile];
+    zz = a.zc[J * kTile + lane];
+    ww = a.wc[J * kTile + lane];
+  };
+  auto multiply = [&](const float2 (&h)[kRowsPerWave], const float2 &zj, const float2 &wj, int jj) {
     float2 cz = make_float2(0.f, 0.f), cw = make_float2(0.f, 0.f);
 #pragma unroll
     for (int q = 0; q < kRowsPerWave; ++q) {
@@ -207,7 +211,21 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
       cz = cmac_conj(cz, h[q], zI[q]);
       cw = cmac_conj(cw, h[q], wI[q]);
     }
-    colbuf[J - J0][wave][lane] = make_float4(cz.x, cz.y, cw.x, cw.y);
+    colbuf[jj][wave][lane] = make_float4(cz.x, cz.y, cw.x, cw.y);
+  };
+  // Two statically named register sets (ping-pong): the loads of tile jj+1
+  // are issued before tile jj is multiplied.  Tiles past the end of a short
+  // run are clamped to its last tile (a re-read that hits in cache) and not
+  // multiplied.  (16-byte loads covering two rows per instruction measured
+  // 2x slower here than these 8-byte row loads.)
+  const int nrun = J1 - J0;
+  issue(hA, zA, wA, 0);
+#pragma unroll
+  for (int jj = 0; jj < CH; jj += 2) {
+    if (jj + 1 < CH) issue(hB, zB, wB, jj + 1);
+    if (jj < nrun) multiply(hA, zA, wA, jj);
+    if (jj + 2 < CH) issue(hA, zA, wA, jj + 2);
+    if (jj + 1 < CH && jj + 1 < nrun) multiply(hB, zB, wB, jj + 1);
   }
 
   // Row partials: 16 rows x (yz, yw) = 64 floats per lane, summed over the 64
