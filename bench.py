@@ -28,6 +28,7 @@ sys.path.insert(0, str(ROOT))
 METRIC = "pulses/sec (Gram update + 20 FISTA iters) at 64×64 scene; % HBM/MFMA peak"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_haar64.json"
 KERNEL_SOURCES = {"step": "paper_2603_08582_amd/csrc/fista.hip",
                   "gram": "paper_2603_08582_amd/csrc/gram.hip"}
@@ -151,9 +152,17 @@ def main():
     step_avg = step_ms / max(step_n, 1)
     gram_flops = 4.0 * K * N * (N + 1)          # Hermitian upper triangle, per pulse
     step_bytes = 4.0 * N * (N + 1)              # upper-triangle complex64 H, per FISTA step
-    rl_gram = {"bound": "mfma", "achieved": gram_flops / (gram_avg * 1e-3) / 1e12,
-               "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": traffic_for("gram"),
-               "kernel": "k_gram_fp32", "avg_ms": gram_avg, "launches": gram_n}
+    if s.precision == "split_bf16":
+        # three BF16 products per FP32 product (hi*hi + hi*lo + lo*hi)
+        rl_gram = {"bound": "mfma", "achieved": 3 * gram_flops / (gram_avg * 1e-3) / 1e12,
+                   "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "bf16x3",
+                   "traffic": None, "kernel": "k_gram_bf16x3", "avg_ms": gram_avg,
+                   "launches": gram_n}
+    else:
+        rl_gram = {"bound": "mfma", "achieved": gram_flops / (gram_avg * 1e-3) / 1e12,
+                   "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "fp32",
+                   "traffic": traffic_for("gram"), "kernel": "k_gram_fp32", "avg_ms": gram_avg,
+                   "launches": gram_n}
     rl_step = {"bound": "hbm", "achieved": step_bytes / (step_avg * 1e-3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step"),
                "kernel": "k_fista_step", "avg_ms": step_avg, "launches": step_n}

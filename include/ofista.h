@@ -52,7 +52,8 @@ typedef enum ofista_status {
 
 enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1 };
 /* Arithmetic of the Gram update: FP32 MFMA, or BF16 MFMA on a hi+lo split of
-   each operand (three products, FP32 accumulation). */
+   each operand (three products, FP32 accumulation; needs n_freq divisible by
+   32, else OFISTA_E_UNSUPPORTED). */
 enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
 /* L_n rule: RUNNING = rho_{n-1} + sigma_n^2 (rho: Rayleigh quotient of a power
    vector advanced once per FISTA step on the current H); BOUND = L_{n-1} +
@@ -162,6 +163,11 @@ ofista_status ofista_echo(struct ofista_ctx *ctx, int32_t s, const void *d_rho,
    N x N complex64 matrix (row-major; N <= 16384, else OFISTA_E_UNSUPPORTED).  ofista_vector: which = 0 b, 1 c_hat,
    2 power vector w (unnormalised), N complex64 each. */
 ofista_status ofista_rows(struct ofista_ctx *ctx, int32_t s, void *d_out);
+/* Sampled entries out[t] = H_n[i[t], j[t]] for t < n, read from the packed
+   storage at any N.  d_i, d_j: device int32 arrays of n pixel indices;
+   d_out: device, n complex64.  Indices outside [0, N) give NaN. */
+ofista_status ofista_gram_entries(struct ofista_ctx *ctx, int32_t n, const int32_t *d_i,
+                                  const int32_t *d_j, void *d_out);
 ofista_status ofista_gram(struct ofista_ctx *ctx, void *d_out);
 ofista_status ofista_vector(struct ofista_ctx *ctx, int32_t which, void *d_out);
 
@@ -177,8 +183,9 @@ ofista_status ofista_import_state(struct ofista_ctx *ctx, const void *d_buf);
    ofista_kernel_time synchronises and returns the summed milliseconds and the
    launch count since enabling.  kernel: 0 Gram update (with the correlation
    b += A_s^H d fused in), 1 FISTA-step tile pass (the H z / H w streaming),
-   2 rows, 3 unused, 4 scalars, 5 FISTA-step update (slot sums, shrink,
-   momentum, power vector). */
+   2 rows, 3 correlation (separate launch on the split-BF16 path only),
+   4 scalars, 5 FISTA-step update (slot sums, shrink, momentum, power
+   vector). */
 ofista_status ofista_profile(struct ofista_ctx *ctx, int32_t enable);
 ofista_status ofista_kernel_time(struct ofista_ctx *ctx, int32_t kernel,
                                  double *total_ms, int64_t *launches);

@@ -48,8 +48,9 @@ def clean_echo(position, pixel_xyz, freqs, rho, support=None, sign: int = -1):
 
 
 def echoes(wl, sign: int = -1, with_noise: bool = True,
-           with_phase_error: bool = True) -> np.ndarray:
-    """Synthetic radar returns for every pulse of a workload (P x K complex128).
+           with_phase_error: bool = True, pulses=None) -> np.ndarray:
+    """Synthetic radar returns for the pulses of a workload (P x K complex128;
+    rows not listed in `pulses`, when given, stay zero).
 
     d_s = exp(i phi_s) F_s rho + sigma_s eps_s, with eps_s the workload's
     unit-variance complex draws and sigma_s^2 = (|F_s rho|^2 / K) 10^(-SNR/10),
@@ -60,7 +61,7 @@ def echoes(wl, sign: int = -1, with_noise: bool = True,
     f = wl.freqs()
     P, K = s.n_pulses, s.n_freq
     d = np.zeros((P, K), dtype=np.complex128)
-    for p in range(P):
+    for p in (range(P) if pulses is None else pulses):
         clean = clean_echo(wl.positions[p], pix, f, wl.rho, wl.support, sign)
         if with_phase_error:
             clean = clean * np.exp(1j * wl.phase_err[p])

@@ -186,6 +186,239 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
   }
 }
 
+constexpr int kCorrPix = 64;    // pixels per workgroup
+constexpr int kCorrGroups = 4;  // frequency groups per workgroup (k = g, g+4, ...)
+
+// b += A^H (d e^{-i phi}); at the first pulse also max_i |Delta b_i| for
+// lambda.  Workgroup = 64 pixels x 4 frequency groups; the 4 group sums are
+// added in fixed order.
+__global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__ A,
+                                              const float2 *__restrict__ d,
+                                              float cphi, float sphi,
+                                              float2 *__restrict__ b,
+                                              DevScalars *__restrict__ scal, int first) {
+  extern __shared__ float2 dl[];  // K rotated samples
+  __shared__ float2 part[kCorrGroups][kCorrPix];
+  __shared__ float red[kCorrPix];
+  for (int k = threadIdx.x; k < g.K; k += 256) {
+    const float2 v = d[k];
+    // d e^{-i phi} = (v.x + i v.y)(cos phi - i sin phi)
+    dl[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
+  }
+  __syncthreads();
+  const int px = threadIdx.x & (kCorrPix - 1);
+  const int grp = threadIdx.x / kCorrPix;
+  const int i = blockIdx.x * kCorrPix + px;  // < Npad (Npad is a multiple of 64)
+  float re = 0.f, im = 0.f;
+  for (int k = grp; k < g.K; k += kCorrGroups) {
+    const float2 a = A[static_cast<size_t>(k) * g.Npad + i];
+    const float2 x = dl[k];
+    // conj(a) * x
+    re += a.x * x.x + a.y * x.y;
+    im += a.x * x.y - a.y * x.x;
+  }
+  part[grp][px] = make_float2(re, im);
+  __syncthreads();
+  if (grp == 0) {
+    float2 s = part[0][px];
+#pragma unroll
+    for (int q = 1; q < kCorrGroups; ++q) {
+      s.x += part[q][px].x;
+      s.y += part[q][px].y;
+    }
+    float2 bi = b[i];
+    bi.x += s.x;
+    bi.y += s.y;
+    b[i] = bi;
+    red[px] = sqrtf(s.x * s.x + s.y * s.y);
+  }
+  if (first) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int q = 0; q < kCorrPix; ++q) m = fmaxf(m, red[q]);
+      // max of non-negative floats: integer order equals float order
+      atomicMax(&scal->dbmax_bits, __float_as_uint(m));
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Precision form: split-BF16 Gram update.  Each FP32 component x of A_s is
+// split once per pulse into hi = bf16(x) and lo = bf16(x - hi) (round to
+// nearest even), stored pixel-major so that one 16-byte read gives a lane the
+// (re, im) pairs of 4 consecutive frequencies.  Per 8 frequencies a wave
+// issues v_mfma_f32_32x32x16_bf16 three times per plane (hi*hi + hi*lo +
+// lo*hi, the lo*lo term dropped) accumulating in FP32: Re uses B = (ar', ai')
+// and Im uses B = (ai', -ar'), as in the FP32 kernel.  A and B fragments use
+// the same lane/element-to-k assignment, so every (frequency, component)
+// pair is contracted with its own partner whatever that assignment is.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ float bf16_to_float(unsigned h) { return __uint_as_float(h << 16); }
+
+constexpr int kSplitTile = 64;
+
+// A (K x Npad complex64, frequency rows) -> Ahi, Alo (Npad x K words, word =
+// re in the low half, im in the high half).  64 x 64 transpose through LDS.
+__global__ __launch_bounds__(256) void k_split_bf16(int K, int Npad, const float2 *__restrict__ A,
+                                                    unsigned *__restrict__ Ahi,
+                                                    unsigned *__restrict__ Alo) {
+  __shared__ float2 tile[kSplitTile][kSplitTile + 1];
+  const int p0 = blockIdx.x * kSplitTile, k0 = blockIdx.y * kSplitTile;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int idx = threadIdx.x + 256 * r;
+    const int f = idx >> 6, px = idx & 63;
+    tile[f][px] = k0 + f < K ? A[static_cast<size_t>(k0 + f) * Npad + p0 + px] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int idx = threadIdx.x + 256 * r;
+    const int px = idx >> 6, f = idx & 63;
+    if (k0 + f < K) {
+      const float2 v = tile[f][px];
+      const unsigned hr = bf16_rne(v.x), hi = bf16_rne(v.y);
+      const unsigned lr = bf16_rne(v.x - bf16_to_float(hr)), li = bf16_rne(v.y - bf16_to_float(hi));
+      const size_t o = static_cast<size_t>(p0 + px) * K + k0 + f;
+      Ahi[o] = hr | (hi << 16);
+      Alo[o] = lr | (li << 16);
+    }
+  }
+}
+
+constexpr int kBfKB = 32;             // frequencies per LDS stage
+constexpr int kBfStride = kBfKB + 4;  // words per column in LDS (padding against bank conflicts)
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// (ar, ai) pairs -> (ai, -ar) pairs: the B operand of the imaginary plane.
+__device__ __forceinline__ u32x4 im_operand(u32x4 v) {
+  return (v >> 16u) | ((v ^ 0x8000u) << 16u);
+}
+
+__global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles_grid,
+                                                     const unsigned *__restrict__ Ahi,
+                                                     const unsigned *__restrict__ Alo,
+                                                     const int2 *__restrict__ tile_ij,
+                                                     float2 *__restrict__ H) {
+  __shared__ unsigned sAh[kTile * kBfStride], sAl[kTile * kBfStride];
+  __shared__ unsigned sBh[kTile * kBfStride], sBl[kTile * kBfStride];
+  const int per = ntiles_grid >> 3;
+  const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int2 ij = tile_ij[logical];
+  if (ij.x < 0) return;
+  const int I = ij.x, J = ij.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int li = lane & 31, h = lane >> 5;
+
+  floatx16 accR, accI;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accR[r] = 0.f;
+    accI[r] = 0.f;
+  }
+  // staging: per plane and operand 64 columns x 32 frequencies = 512 uint4;
+  // element r of a thread is column (t + 256 r) / 8, frequencies
+  // 4 ((t + 256 r) % 8) .. +3 of the stage
+  const u32x4 *gAh = reinterpret_cast<const u32x4 *>(Ahi);
+  const u32x4 *gAl = reinterpret_cast<const u32x4 *>(Alo);
+  const int Kq = K >> 2;  // uint4 per column
+  const int col0 = threadIdx.x >> 3, f40 = threadIdx.x & 7;
+  u32x4 pah[2], pal[2], pbh[2], pbl[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const size_t oI = static_cast<size_t>(I * kTile + col0 + 32 * r) * Kq + f40;
+    const size_t oJ = static_cast<size_t>(J * kTile + col0 + 32 * r) * Kq + f40;
+    pah[r] = gAh[oI];
+    pal[r] = gAl[oI];
+    pbh[r] = gAh[oJ];
+    pbl[r] = gAl[oJ];
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int o = (col0 + 32 * r) * kBfStride + 4 * f40;
+    *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
+    *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
+    *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
+    *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += kBfKB) {
+    const bool more = k0 + kBfKB < K;
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const size_t oI = static_cast<size_t>(I * kTile + col0 + 32 * r) * Kq + ((k0 + kBfKB) >> 2) + f40;
+        const size_t oJ = static_cast<size_t>(J * kTile + col0 + 32 * r) * Kq + ((k0 + kBfKB) >> 2) + f40;
+        pah[r] = gAh[oI];
+        pal[r] = gAl[oI];
+        pbh[r] = gAh[oJ];
+        pbl[r] = gAl[oJ];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kBfKB / 8; ++g) {
+      const int oa = (wi * 32 + li) * kBfStride + 8 * g + 4 * h;
+      const int ob = (wj * 32 + li) * kBfStride + 8 * g + 4 * h;
+      const u32x4 ah = *reinterpret_cast<const u32x4 *>(&sAh[oa]);
+      const u32x4 al = *reinterpret_cast<const u32x4 *>(&sAl[oa]);
+      const u32x4 bh = *reinterpret_cast<const u32x4 *>(&sBh[ob]);
+      const u32x4 bl = *reinterpret_cast<const u32x4 *>(&sBl[ob]);
+      const bf16x8 Ah = as_bf16x8(ah), Al = as_bf16x8(al);
+      const bf16x8 Bh = as_bf16x8(bh), Bl = as_bf16x8(bl);
+      const bf16x8 Bhi = as_bf16x8(im_operand(bh)), Bli = as_bf16x8(im_operand(bl));
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bhi, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bli, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bhi, accI, 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int o = (col0 + 32 * r) * kBfStride + 4 * f40;
+        *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
+        *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
+        *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
+        *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
+      }
+      __syncthreads();
+    }
+  }
+  const int nb = Npad / kTile;
+  const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
+  float2 *Ht = H + tile_index * (kTile * kTile);
+  float2 hv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    hv[r] = Ht[row * kTile + wj * 32 + li];
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int col = wj * 32 + li;
+    hv[r].x += accR[r];
+    hv[r].y += accI[r];
+    if (I == J && row == col) hv[r].y = 0.f;
+    Ht[row * kTile + col] = hv[r];
+  }
+}
+
 // Dense N x N copy of the packed Hermitian H (inspection only).
 __global__ __launch_bounds__(256) void k_gram_dense(int N, int nb, const float2 *__restrict__ H,
                                                     const int *__restrict__ tile_row0,
@@ -204,6 +437,28 @@ __global__ __launch_bounds__(256) void k_gram_dense(int N, int nb, const float2 
   out[idx] = v;
 }
 
+// Sampled entries H[i_n, j_n] of the packed Hermitian H (inspection only).
+__global__ __launch_bounds__(256) void k_gram_entries(int n, int N, const float2 *__restrict__ H,
+                                                      const int *__restrict__ tile_row0,
+                                                      const int *__restrict__ ii,
+                                                      const int *__restrict__ jj,
+                                                      float2 *__restrict__ out) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int i = ii[t], j = jj[t];
+  if (i < 0 || j < 0 || i >= N || j >= N) {
+    out[t] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    return;
+  }
+  const int I = i / kTile, J = j / kTile;
+  if (I <= J) {
+    out[t] = H[static_cast<size_t>(tile_row0[I] + (J - I)) * kTile * kTile + (i % kTile) * kTile + (j % kTile)];
+  } else {
+    const float2 u = H[static_cast<size_t>(tile_row0[J] + (I - J)) * kTile * kTile + (j % kTile) * kTile + (i % kTile)];
+    out[t] = make_float2(u.x, -u.y);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
@@ -212,6 +467,33 @@ hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
   if (g.K > kMaxFreq) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
                      ntiles_grid, A, tile_ij, H, corr);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
+                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
+                       int first, hipStream_t st) {
+  const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
+  hipLaunchKernelGGL(k_corr, dim3(g.Npad / kCorrPix), dim3(256), lds, st, g, A, d,
+                     static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st) {
+  if (g.K % kBfKB != 0) return hipErrorInvalidValue;
+  dim3 sgrid(g.Npad / kSplitTile, (g.K + kSplitTile - 1) / kSplitTile);
+  hipLaunchKernelGGL(k_split_bf16, sgrid, dim3(256), 0, st, g.K, g.Npad, A, Ahi, Alo);
+  hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad, ntiles_grid,
+                     Ahi, Alo, tile_ij, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
+                               const int *ii, const int *jj, float2 *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_entries, dim3((n + 255) / 256), dim3(256), 0, st, n, g.N, H, tile_row0,
+                     ii, jj, out);
   return hipGetLastError();
 }
 

@@ -68,9 +68,9 @@ struct DevState {
   int *tile_row0;    // index of tile (I, I)
   WorkItem *items;
   double2 *echo_tmp; // K clean-echo sums
-  // split-BF16 operands of the Gram update (NULL for FP32)
-  unsigned short *Ahi;
-  unsigned short *Alo;
+  // split-BF16 operands of the Gram update, Npad x K words (NULL for FP32)
+  unsigned *Ahi;
+  unsigned *Alo;
 };
 
 // ---- rows.hip ----
@@ -86,6 +86,14 @@ hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
                          double *sig2, hipStream_t st);
 
 // ---- gram.hip ----
+// Correlation as its own launch (split-BF16 path): b += A^H (d e^{-i phi}).
+hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
+                       double cos_c, double sin_c, float2 *b, DevScalars *scal,
+                       int first, hipStream_t st);
+// Split-BF16 Gram update (K must be a multiple of 32): split A into the
+// pixel-major hi/lo planes, then H += A^H A from three BF16 products.
+hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st);
 // Correlation fused into the Gram update: b += A^H (d e^{-i phi}).
 struct CorrArgs {
   const float2 *d;
@@ -97,6 +105,8 @@ struct CorrArgs {
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
                             hipStream_t st);
+hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
+                               const int *ii, const int *jj, float2 *out, hipStream_t st);
 hipError_t launch_gram_dense(const Geom &g, const float2 *H,
                              const int *tile_row0, float2 *out,
                              hipStream_t st);

@@ -76,8 +76,8 @@ ofista_status check(const ofista_config *c, std::string *why) {
   if (c->momentum < OFISTA_MOMENTUM_FISTA || c->momentum > OFISTA_MOMENTUM_ISTA)
     return bad("unknown momentum mode");
   if (c->record_every < 0) return bad("record_every must be >= 0");
-  if (c->precision == OFISTA_PREC_SPLIT_BF16) {
-    if (why) *why = "split-BF16 Gram update not available in this build";
+  if (c->precision == OFISTA_PREC_SPLIT_BF16 && c->n_freq % 32 != 0) {
+    if (why) *why = "split-BF16 Gram update needs n_freq divisible by 32";
     return OFISTA_E_UNSUPPORTED;
   }
   if (c->record_every > 0) {
@@ -128,6 +128,10 @@ Layout layout(const ofista_config *c) {
   L.items = take(L.nitems * sizeof(WorkItem));
   L.echo_tmp = take(L.K * sizeof(double2));
   L.Ahi = L.Alo = 0;
+  if (c->precision == OFISTA_PREC_SPLIT_BF16) {
+    L.Ahi = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
+    L.Alo = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
+  }
   L.total = o;
   return L;
 }
@@ -324,6 +328,8 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   d.tile_row0 = reinterpret_cast<int *>(base + L.tile_row0);
   d.items = reinterpret_cast<WorkItem *>(base + L.items);
   d.echo_tmp = reinterpret_cast<double2 *>(base + L.echo_tmp);
+  d.Ahi = L.Ahi ? reinterpret_cast<unsigned *>(base + L.Ahi) : nullptr;
+  d.Alo = L.Alo ? reinterpret_cast<unsigned *>(base + L.Alo) : nullptr;
 
   // host tables
   const int nb = L.nb;
@@ -395,7 +401,16 @@ ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, d
     ProfScope p(c, kProfRows);
     OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
   }
-  {
+  if (c->cfg.precision == OFISTA_PREC_SPLIT_BF16) {
+    {
+      ProfScope p(c, kProfCorr);
+      OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
+                           std::sin(phase_corr), d.b, d.scal, first, c->st));
+    }
+    ProfScope p(c, kProfGram);
+    OF_CK(c, launch_gram_bf16x3(c->g, d.A, d.Ahi, d.Alo, d.H, d.tile_ij,
+                                static_cast<int>(c->L.ntiles_grid), c->st));
+  } else {
     ProfScope p(c, kProfGram);
     CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
@@ -502,6 +517,16 @@ ofista_status ofista_gram(ofista_ctx *c, void *d_out) {
   if (!d_out) return OFISTA_E_ARG;
   if (c->L.N > 16384) return OFISTA_E_UNSUPPORTED;  // inspection of small problems only
   OF_CK(c, launch_gram_dense(c->g, c->d.H, c->d.tile_row0, static_cast<float2 *>(d_out), c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_gram_entries(ofista_ctx *c, int32_t n, const int32_t *d_i, const int32_t *d_j,
+                                  void *d_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (n < 0 || (n > 0 && (!d_i || !d_j || !d_out))) return OFISTA_E_ARG;
+  OF_CK(c, launch_gram_entries(c->g, c->d.H, c->d.tile_row0, n, d_i, d_j,
+                               static_cast<float2 *>(d_out), c->st));
   return OFISTA_OK;
 }
 

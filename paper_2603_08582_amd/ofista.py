@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "ofista_echo": (i32, [vp, i32, vp, vp, f64, f64, vp]),
         "ofista_rows": (i32, [vp, i32, vp]),
         "ofista_gram": (i32, [vp, vp]),
+        "ofista_gram_entries": (i32, [vp, i32, vp, vp, vp]),
         "ofista_vector": (i32, [vp, i32, vp]),
         "ofista_export_state": (i32, [vp, vp]),
         "ofista_import_state": (i32, [vp, vp]),
@@ -222,6 +223,16 @@ class OnlineFista:
     def gram(self):
         o = torch.empty((self.N, self.N), dtype=torch.complex64, device=self.device)
         self._check(self._lib.ofista_gram(self._ctx, _ptr(o)))
+        return o
+
+    def gram_entries(self, i, j):
+        """H_n[i[t], j[t]] for pixel index sequences i, j (any N)."""
+        ii = torch.as_tensor(np.asarray(i), dtype=torch.int32).to(self.device).contiguous()
+        jj = torch.as_tensor(np.asarray(j), dtype=torch.int32).to(self.device).contiguous()
+        if ii.shape != jj.shape or ii.dim() != 1:
+            raise ValueError("i and j must be 1-D of equal length")
+        o = torch.empty(ii.numel(), dtype=torch.complex64, device=self.device)
+        self._check(self._lib.ofista_gram_entries(self._ctx, ii.numel(), _ptr(ii), _ptr(jj), _ptr(o)))
         return o
 
     def vector(self, which: str):

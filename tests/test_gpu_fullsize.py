@@ -98,9 +98,10 @@ def test_large_full_run_sampled_entries():
     ii = rng.integers(0, N, 24)
     jj = rng.integers(0, N, 24)
     ii[:4] = jj[:4]  # a few diagonal entries
-    H = g.gram()
-    Hs = H[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].cpu().numpy()
-    del H
+    Hs = g.gram_entries(ii, jj).cpu().numpy()
+    Hd = g.gram()  # the dense expansion agrees with the packed entries
+    assert np.array_equal(Hd[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].cpu().numpy(), Hs)
+    del Hd
     torch.cuda.empty_cache()
     scale = P * K
     for n, (i, j) in enumerate(zip(ii, jj)):
