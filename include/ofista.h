@@ -85,7 +85,8 @@ typedef struct ofista_config {
   int32_t lipschitz;       /* OFISTA_LIP_*                                     */
   int32_t momentum;        /* OFISTA_MOMENTUM_*                                */
   int32_t record_every;    /* > 0: keep what ofista_backward needs, with a
-                              state checkpoint every record_every pulses     */
+                              state checkpoint every record_every pulses
+                              (see ofista_backward)                          */
   int32_t max_pulses;      /* pulses that can be recorded (record_every > 0) */
   int32_t max_iters;       /* inner steps per reconstruct that can be
                               recorded (record_every > 0)                    */
@@ -173,10 +174,36 @@ ofista_status ofista_vector(struct ofista_ctx *ctx, int32_t which, void *d_out);
 
 /* Resumable state record (n, t, L, lambda, power vector, c_hat, b, H), so that
    a run split at any pulse and resumed equals the uninterrupted run.  The
-   buffer is caller-owned device memory of ofista_state_bytes(cfg) bytes. */
+   buffer is caller-owned device memory of ofista_state_bytes(cfg) bytes;
+   alignment padding inside it is left unwritten.  Export synchronises the
+   stream; import synchronises it and forgets any recorded history. */
 size_t ofista_state_bytes(const ofista_config *cfg);
 ofista_status ofista_export_state(struct ofista_ctx *ctx, void *d_buf);
 ofista_status ofista_import_state(struct ofista_ctx *ctx, const void *d_buf);
+
+/* Differentiation form (Section III-C run as an unrolled, differentiable map).
+   With record_every > 0 in the config, every pushed pulse (data, position,
+   phase_corr) and the step count of the reconstruct that follows it are
+   recorded, with a state checkpoint every record_every pulses (at most
+   max_pulses pulses, at most max_iters steps per reconstruct, exactly one
+   reconstruct per pulse; otherwise OFISTA_E_STATE / OFISTA_E_ARG).
+
+   ofista_backward: given d_grad_img (device, N complex64) = dLoss/dRe x +
+   i dLoss/dIm x for the current image x = W c_hat of a real loss, returns
+   *grad_lambda = dLoss/dlambda (lambda as an absolute value, see
+   ofista_set_lambda) and grad_phase[n] = dLoss/dphase_corr_n for every pulse
+   pushed since the last reset (host array of n_pulses doubles).  H, L_n and
+   the momentum sequence do not depend on these parameters; the reverse pass
+   re-runs each segment from its checkpoint (bitwise the same forward) and
+   walks its pulses and steps backwards.  Synchronises the stream; the online
+   state after the call is the state before it.  OFISTA_E_STATE when not
+   recording or nothing was pushed. */
+ofista_status ofista_backward(struct ofista_ctx *ctx, const void *d_grad_img,
+                              double *grad_lambda, double *grad_phase);
+
+/* Use the absolute l1 weight lambda from now on (lambda_relative is turned
+   off).  Takes effect for the next FISTA step. */
+ofista_status ofista_set_lambda(struct ofista_ctx *ctx, double lambda);
 
 /* Per-kernel timing with HIP events on the ctx's stream.  While enabled, every
    launch of the named kernel class is bracketed by a pair of events.

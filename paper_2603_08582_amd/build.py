@@ -23,7 +23,7 @@ LIB = HERE / "libofista.so"
 BUILD = HERE.parent / "_build" / "ofista"
 
 ARCH = os.environ.get("OFISTA_ARCH", "gfx950")
-SOURCES = ["rows.hip", "gram.hip", "fista.hip", "runtime.cpp"]
+SOURCES = ["rows.hip", "gram.hip", "fista.hip", "adjoint.hip", "runtime.cpp"]
 
 
 def hipcc() -> str:

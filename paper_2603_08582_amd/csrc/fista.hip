@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
     if (live) {
       const float gx = s.x - bi.x, gy = s.y - bi.y;
       const float ux = z.x - tau * gx, uy = z.y - tau * gy;
+      if (a.urec) a.urec[i] = make_float2(ux, uy);  // kept for the reverse pass
       const float mag = sqrtf(ux * ux + uy * uy);
       float cx = 0.f, cy = 0.f;
       if (mag > alpha) {

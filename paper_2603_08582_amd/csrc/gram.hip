@@ -196,7 +196,8 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__
                                               const float2 *__restrict__ d,
                                               float cphi, float sphi,
                                               float2 *__restrict__ b,
-                                              DevScalars *__restrict__ scal, int first) {
+                                              DevScalars *__restrict__ scal, int first,
+                                              float2 *__restrict__ delta) {
   extern __shared__ float2 dl[];  // K rotated samples
   __shared__ float2 part[kCorrGroups][kCorrPix];
   __shared__ float red[kCorrPix];
@@ -226,10 +227,13 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__
       s.x += part[q][px].x;
       s.y += part[q][px].y;
     }
-    float2 bi = b[i];
-    bi.x += s.x;
-    bi.y += s.y;
-    b[i] = bi;
+    if (b) {
+      float2 bi = b[i];
+      bi.x += s.x;
+      bi.y += s.y;
+      b[i] = bi;
+    }
+    if (delta) delta[i] = s;
     red[px] = sqrtf(s.x * s.x + s.y * s.y);
   }
   if (first) {
@@ -472,10 +476,10 @@ hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
 
 hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
                        double cos_c, double sin_c, float2 *b, DevScalars *scal,
-                       int first, hipStream_t st) {
+                       int first, hipStream_t st, float2 *delta) {
   const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
   hipLaunchKernelGGL(k_corr, dim3(g.Npad / kCorrPix), dim3(256), lds, st, g, A, d,
-                     static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first);
+                     static_cast<float>(cos_c), static_cast<float>(sin_c), b, scal, first, delta);
   return hipGetLastError();
 }
 

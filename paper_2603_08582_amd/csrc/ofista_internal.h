@@ -78,6 +78,9 @@ hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
                        int dict, int levels, hipStream_t st);
 hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
                         int levels, hipStream_t st);
+// c = W^T x (adjoint of the image synthesis), padded to Npad.
+hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, int dict, int levels,
+                                hipStream_t st);
 hipError_t launch_echo(const Geom &g, const double *pos, int s,
                        const float2 *rho, const float2 *noise, double snr_db,
                        double phase_err, double2 *tmp, float2 *out,
@@ -87,9 +90,10 @@ hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
 
 // ---- gram.hip ----
 // Correlation as its own launch (split-BF16 path): b += A^H (d e^{-i phi}).
+// With b == NULL only Delta b is written (to delta, if set).
 hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
                        double cos_c, double sin_c, float2 *b, DevScalars *scal,
-                       int first, hipStream_t st);
+                       int first, hipStream_t st, float2 *delta = nullptr);
 // Split-BF16 Gram update (K must be a multiple of 32): split A into the
 // pixel-major hi/lo planes, then H += A^H A from three BF16 products.
 hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
@@ -127,6 +131,7 @@ struct StepArgs {
   const DevScalars *scal;
   const WorkItem *items;
   const int *tile_row0;
+  float2 *urec;  // if set, the update stores u = z - tau (H z - b) here
   int nb, N, nitems, chunk;
   float beta;
 };
@@ -139,5 +144,28 @@ hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
 hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N,
                              int Npad, int nb, hipStream_t st);
+
+// ---- adjoint.hip ----
+struct AdjArgs {
+  const float4 *Q;
+  const DevScalars *scal;          // tau_n, alpha_n of the pulse being reversed
+  const float2 *u_prev;            // u of the step whose ubar is formed
+  const float2 *ubar_cur;          // ubar_k (input of the update)
+  float2 *ubar_next;               // ubar of the next reverse step
+  const float2 *cpart_cur;         // partial adjoint P_{k-1}
+  float2 *cpart_next;              // P_{k-2}
+  float2 *bbar;                    // adjoint of b_n (this pulse)
+  float2 *chat_bar;                // adjoint of the coefficients entering / leaving the pulse
+  float2 *Bbar;                    // sum of bbar over later pulses
+  double *alpha_parts;             // nb parts of alphabar for the step whose ubar is formed
+  const double *alpha_parts_all;   // all parts of the pulse (k_adj_pulse)
+  int nb, N, chunk, last;
+  float beta_prev;
+};
+hipError_t launch_adj_start(const AdjArgs &a, hipStream_t st);
+hipError_t launch_adj_update(const AdjArgs &a, hipStream_t st);
+hipError_t launch_adj_pulse(const AdjArgs &a, int n_parts, int Npad, const float2 *dB,
+                            double *lam_out, double *phase_out, hipStream_t st);
+hipError_t launch_set_lambda(DevScalars *scal, double lam, hipStream_t st);
 
 }  // namespace ofista

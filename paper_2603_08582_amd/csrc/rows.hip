@@ -167,6 +167,22 @@ __global__ __launch_bounds__(kHaarThreads) void k_image_haar(Geom g, int levels,
   for (int i = threadIdx.x; i < g.N; i += kHaarThreads) x[i] = buf[i];
 }
 
+// c = W^T x for the Haar dictionary (analysis of one image; single workgroup).
+__global__ __launch_bounds__(kHaarThreads) void k_analysis_haar(Geom g, int levels,
+                                                                const float2 *__restrict__ x,
+                                                                float2 *__restrict__ c) {
+  extern __shared__ float2 buf[];
+  for (int i = threadIdx.x; i < g.N; i += kHaarThreads) buf[i] = x[i];
+  __syncthreads();
+  for (int lev = 0; lev < levels; ++lev) haar_level_analysis<kHaarMaxPer>(buf, g.nx, g.nx >> lev);
+  for (int i = threadIdx.x; i < g.Npad; i += kHaarThreads) c[i] = i < g.N ? buf[i] : make_float2(0.f, 0.f);
+}
+
+__global__ void k_copy_pad_c64(const float2 *__restrict__ src, float2 *__restrict__ dst, int n, int npad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npad) dst[i] = i < n ? src[i] : make_float2(0.f, 0.f);
+}
+
 __global__ void k_copy_c64(const float2 *__restrict__ src, float2 *__restrict__ dst, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -336,6 +352,17 @@ hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
     hipLaunchKernelGGL(k_image_haar, dim3(1), dim3(kHaarThreads), lds, st, g, levels, c, x);
   } else {
     hipLaunchKernelGGL(k_copy_c64, dim3((g.N + 255) / 256), dim3(256), 0, st, c, x, g.N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, int dict, int levels,
+                                hipStream_t st) {
+  if (dict == 1) {
+    const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
+    hipLaunchKernelGGL(k_analysis_haar, dim3(1), dim3(kHaarThreads), lds, st, g, levels, x, c);
+  } else {
+    hipLaunchKernelGGL(k_copy_pad_c64, dim3((g.Npad + 255) / 256), dim3(256), 0, st, x, c, g.N, g.Npad);
   }
   return hipGetLastError();
 }

@@ -27,8 +27,21 @@ struct Layout {
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
       sig2, gtoep, tile_ij, tile_row0, items, echo_tmp, Ahi, Alo;
+  // differentiation form (record_every > 0)
+  int rec_every = 0, rec_pulses = 0, rec_iters = 0, n_ckpt = 0;
+  size_t state_bytes = 0;
+  size_t ckpt = 0, pulses_d = 0, seg_H = 0, seg_u = 0, seg_db = 0, seg_scal = 0, chat_bar = 0,
+         ubar0 = 0, ubar1 = 0, cpart0 = 0, cpart1 = 0, bbar = 0, Bbar = 0, alpha_parts = 0,
+         lam_dev = 0, phase_dev = 0;
   size_t total = 0;
 };
+
+size_t state_record_bytes(const Layout &L) {
+  return align_up(16 * sizeof(double)) + align_up(sizeof(DevScalars)) +
+         2 * align_up(2 * L.nb * sizeof(double)) +
+         3 * align_up(static_cast<size_t>(L.Npad) * sizeof(float2)) +
+         L.ntiles * kTile * kTile * sizeof(float2);
+}
 
 size_t count_items(int nb, int chunk) {
   size_t n = 0;
@@ -80,10 +93,8 @@ ofista_status check(const ofista_config *c, std::string *why) {
     if (why) *why = "split-BF16 Gram update needs n_freq divisible by 32";
     return OFISTA_E_UNSUPPORTED;
   }
-  if (c->record_every > 0) {
-    if (why) *why = "recording for backward not available in this build";
-    return OFISTA_E_UNSUPPORTED;
-  }
+  if (c->record_every > 0 && (c->max_pulses < 1 || c->max_iters < 1))
+    return bad("recording needs max_pulses >= 1 and max_iters >= 1");
   for (int i = 0; i < 3 * c->n_pos; ++i)
     if (!std::isfinite(c->pos_xyz[i])) return bad("pos_xyz must be finite");
   return OFISTA_OK;
@@ -132,6 +143,30 @@ Layout layout(const ofista_config *c) {
     L.Ahi = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
     L.Alo = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
   }
+  L.state_bytes = state_record_bytes(L);
+  if (c->record_every > 0) {
+    L.rec_every = c->record_every;
+    L.rec_pulses = c->max_pulses;
+    L.rec_iters = c->max_iters;
+    L.n_ckpt = (L.rec_pulses + L.rec_every - 1) / L.rec_every + 1;  // + the live state
+    const int R = std::min(L.rec_every, L.rec_pulses);
+    L.ckpt = take(static_cast<size_t>(L.n_ckpt) * align_up(L.state_bytes));
+    L.pulses_d = take(static_cast<size_t>(L.rec_pulses) * L.K * sizeof(float2));
+    L.seg_H = take(static_cast<size_t>(R) * L.ntiles * kTile * kTile * sizeof(float2));
+    L.seg_u = take(static_cast<size_t>(R) * L.rec_iters * vec);
+    L.seg_db = take(static_cast<size_t>(R) * vec);
+    L.seg_scal = take(static_cast<size_t>(R) * sizeof(DevScalars));
+    L.chat_bar = take(vec);
+    L.ubar0 = take(vec);
+    L.ubar1 = take(vec);
+    L.cpart0 = take(vec);
+    L.cpart1 = take(vec);
+    L.bbar = take(vec);
+    L.Bbar = take(vec);
+    L.alpha_parts = take(static_cast<size_t>(L.rec_iters) * L.nb * sizeof(double));
+    L.lam_dev = take(static_cast<size_t>(L.rec_pulses) * sizeof(double));
+    L.phase_dev = take(static_cast<size_t>(L.rec_pulses) * sizeof(double));
+  }
   L.total = o;
   return L;
 }
@@ -176,6 +211,15 @@ struct ofista_ctx {
   int64_t G = 0;       // FISTA steps since reset
   bool have_iter = false;
   double t = 1.0;
+  // differentiation form: what was pushed, and the segment being re-run
+  struct PulseRec {
+    int s;
+    double phase;
+    int iters;       // -1: no reconstruct followed this push
+    double t_start;  // momentum scalar at the start of that reconstruct
+  };
+  std::vector<PulseRec> rec;
+  char *base = nullptr;  // workspace
   // profiling
   bool prof = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
@@ -251,6 +295,7 @@ ofista_status do_reset(ofista_ctx *c) {
   c->G = 0;
   c->have_iter = false;
   c->t = 1.0;
+  c->rec.clear();
   return OFISTA_OK;
 }
 
@@ -269,11 +314,7 @@ size_t ofista_workspace_bytes(const ofista_config *cfg) {
 
 size_t ofista_state_bytes(const ofista_config *cfg) {
   if (check(cfg, nullptr) != OFISTA_OK) return 0;
-  const Layout L = layout(cfg);
-  return align_up(16 * sizeof(double)) + align_up(sizeof(DevScalars)) +
-         2 * align_up(2 * L.nb * sizeof(double)) +
-         3 * align_up(static_cast<size_t>(L.Npad) * sizeof(float2)) +
-         L.ntiles * kTile * kTile * sizeof(float2);
+  return state_record_bytes(layout(cfg));
 }
 
 ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t ws_bytes,
@@ -307,6 +348,7 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   g.df = cfg->dfreq_hz;
 
   char *base = static_cast<char *>(d_workspace);
+  c->base = base;
   DevState &d = c->d;
   d.H = reinterpret_cast<float2 *>(base + L.H);
   d.A = reinterpret_cast<float2 *>(base + L.A);
@@ -390,16 +432,29 @@ ofista_status ofista_reset(ofista_ctx *c) {
   return do_reset(c);
 }
 
-ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr) {
-  ofista_status st = usable(c);
-  if (st != OFISTA_OK) return st;
-  if (!d_pulse || !std::isfinite(phase_corr)) return OFISTA_E_ARG;
-  if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
+}  // extern "C"
+
+namespace {
+
+float2 *seg_ptr(ofista_ctx *c, size_t off, size_t idx, size_t stride) {
+  return reinterpret_cast<float2 *>(c->base + off + idx * stride);
+}
+
+// One pulse: rows, H and b updates, scalars.  seg_j >= 0 while the backward
+// pass re-runs pulse seg_j of a segment: then also keep H_n, Delta b_n and the
+// scalars of this pulse.
+ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr, int seg_j) {
   const DevState &d = c->d;
+  const Layout &L = c->L;
   const int first = c->n == 0 ? 1 : 0;
   {
     ProfScope p(c, kProfRows);
     OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
+  }
+  if (seg_j >= 0) {
+    OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
+                         std::sin(phase_corr), nullptr, d.scal, 0, c->st,
+                         seg_ptr(c, L.seg_db, seg_j, static_cast<size_t>(L.Npad) * sizeof(float2))));
   }
   if (c->cfg.precision == OFISTA_PREC_SPLIT_BF16) {
     {
@@ -409,12 +464,12 @@ ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, d
     }
     ProfScope p(c, kProfGram);
     OF_CK(c, launch_gram_bf16x3(c->g, d.A, d.Ahi, d.Alo, d.H, d.tile_ij,
-                                static_cast<int>(c->L.ntiles_grid), c->st));
+                                static_cast<int>(L.ntiles_grid), c->st));
   } else {
     ProfScope p(c, kProfGram);
     CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
-    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(c->L.ntiles_grid), corr,
+    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.ntiles_grid), corr,
                               c->st));
   }
   {
@@ -422,19 +477,26 @@ ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, d
     const int par = static_cast<int>(c->G & 1);
     OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
                             c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
-                            c->L.nb, c->st));
+                            L.nb, c->st));
+  }
+  if (seg_j >= 0) {
+    const size_t hbytes = L.ntiles * kTile * kTile * sizeof(float2);
+    OF_CK(c, hipMemcpyAsync(c->base + L.seg_H + seg_j * hbytes, d.H, hbytes, hipMemcpyDeviceToDevice,
+                            c->st));
+    OF_CK(c, hipMemcpyAsync(c->base + L.seg_scal + seg_j * sizeof(DevScalars), d.scal,
+                            sizeof(DevScalars), hipMemcpyDeviceToDevice, c->st));
   }
   c->n += 1;
   return OFISTA_OK;
 }
 
-ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out) {
-  ofista_status st = usable(c);
-  if (st != OFISTA_OK) return st;
-  if (iters < 0) return OFISTA_E_ARG;
-  if (c->n == 0) return OFISTA_E_STATE;
+// Algorithm 1 with `iters` steps; seg_j >= 0 also keeps u of every step.
+ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, int seg_j,
+                               double *t_start_out) {
   const DevState &d = c->d;
+  const Layout &L = c->L;
   double t = (c->n == 1 || c->cfg.momentum == OFISTA_MOMENTUM_RESTART) ? 1.0 : c->t;
+  if (t_start_out) *t_start_out = t;
   for (int k = 0; k < iters; ++k) {
     const int p = static_cast<int>(c->G & 1);
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
@@ -454,10 +516,13 @@ ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out)
     a.scal = d.scal;
     a.items = d.items;
     a.tile_row0 = d.tile_row0;
-    a.nb = c->L.nb;
-    a.N = c->L.N;
-    a.nitems = static_cast<int>(c->L.nitems);
-    a.chunk = c->L.chunk;
+    a.urec = seg_j >= 0 ? seg_ptr(c, L.seg_u, static_cast<size_t>(seg_j) * L.rec_iters + k,
+                                  static_cast<size_t>(L.Npad) * sizeof(float2))
+                        : nullptr;
+    a.nb = L.nb;
+    a.N = L.N;
+    a.nitems = static_cast<int>(L.nitems);
+    a.chunk = L.chunk;
     a.beta = static_cast<float>(beta);
     {
       ProfScope ps(c, kProfStep);
@@ -473,9 +538,201 @@ ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out)
   c->t = t;
   if (iters > 0) c->have_iter = true;
   if (d_coef_out) {
-    OF_CK(c, hipMemcpyAsync(d_coef_out, d.cbuf[c->G & 1], static_cast<size_t>(c->L.N) * sizeof(float2),
+    OF_CK(c, hipMemcpyAsync(d_coef_out, d.cbuf[c->G & 1], static_cast<size_t>(L.N) * sizeof(float2),
                             hipMemcpyDeviceToDevice, c->st));
   }
+  return OFISTA_OK;
+}
+
+ofista_status export_to(ofista_ctx *c, void *d_buf);
+ofista_status import_from(ofista_ctx *c, const void *d_buf);
+
+}  // namespace
+
+extern "C" {
+
+ofista_status ofista_push_pulse(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_pulse || !std::isfinite(phase_corr)) return OFISTA_E_ARG;
+  if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
+  const Layout &L = c->L;
+  if (L.rec_every > 0) {
+    if (c->n >= L.rec_pulses) return OFISTA_E_STATE;  // recording capacity reached
+    if (c->n % L.rec_every == 0) {
+      st = export_to(c, c->base + L.ckpt + static_cast<size_t>(c->n / L.rec_every) * align_up(L.state_bytes));
+      if (st != OFISTA_OK) return st;
+    }
+    OF_CK(c, hipMemcpyAsync(c->base + L.pulses_d + static_cast<size_t>(c->n) * L.K * sizeof(float2), d_pulse,
+                            static_cast<size_t>(L.K) * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+    c->rec.push_back(ofista_ctx::PulseRec{s, phase_corr, -1, 0.0});
+  }
+  return push_impl(c, d_pulse, s, phase_corr, -1);
+}
+
+ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (iters < 0) return OFISTA_E_ARG;
+  if (c->n == 0) return OFISTA_E_STATE;
+  double t0 = 0.0;
+  if (c->L.rec_every > 0) {
+    if (c->rec.empty() || c->rec.back().iters >= 0) return OFISTA_E_STATE;  // one per pulse
+    if (iters > c->L.rec_iters) return OFISTA_E_ARG;
+  }
+  st = reconstruct_impl(c, iters, d_coef_out, -1, &t0);
+  if (st == OFISTA_OK && c->L.rec_every > 0) {
+    c->rec.back().iters = iters;
+    c->rec.back().t_start = t0;
+  }
+  return st;
+}
+
+ofista_status ofista_set_lambda(ofista_ctx *c, double lam) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!std::isfinite(lam) || lam < 0) return OFISTA_E_ARG;
+  c->cfg.lambda = lam;
+  c->cfg.lambda_relative = 0;
+  OF_CK(c, launch_set_lambda(c->d.scal, lam, c->st));
+  return OFISTA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reverse pass of pulse n (re-run as segment slot j).
+ofista_status reverse_pulse(ofista_ctx *c, int n, int j) {
+  const Layout &L = c->L;
+  const DevState &d = c->d;
+  const size_t vbytes = static_cast<size_t>(L.Npad) * sizeof(float2);
+  const size_t hbytes = L.ntiles * kTile * kTile * sizeof(float2);
+  const ofista_ctx::PulseRec &r = c->rec[n];
+  const int m = r.iters < 0 ? 0 : r.iters;
+  float2 *ubar[2] = {seg_ptr(c, L.ubar0, 0, 0), seg_ptr(c, L.ubar1, 0, 0)};
+  float2 *cpart[2] = {seg_ptr(c, L.cpart0, 0, 0), seg_ptr(c, L.cpart1, 0, 0)};
+  double *alpha_parts = reinterpret_cast<double *>(c->base + L.alpha_parts);
+  AdjArgs a{};
+  a.Q = d.Q;
+  a.scal = reinterpret_cast<const DevScalars *>(c->base + L.seg_scal + j * sizeof(DevScalars));
+  a.bbar = seg_ptr(c, L.bbar, 0, 0);
+  a.chat_bar = seg_ptr(c, L.chat_bar, 0, 0);
+  a.Bbar = seg_ptr(c, L.Bbar, 0, 0);
+  a.alpha_parts_all = alpha_parts;
+  a.nb = L.nb;
+  a.N = L.N;
+  a.chunk = L.chunk;
+  const float2 *dB = seg_ptr(c, L.seg_db, j, vbytes);
+  double *lam_out = reinterpret_cast<double *>(c->base + L.lam_dev) + n;
+  double *phase_out = reinterpret_cast<double *>(c->base + L.phase_dev) + n;
+  if (m == 0) {
+    OF_CK(c, launch_fill(a.bbar, static_cast<size_t>(L.Npad) * 2, 0u, c->st));
+    OF_CK(c, launch_adj_pulse(a, 0, L.Npad, dB, lam_out, phase_out, c->st));
+    return OFISTA_OK;
+  }
+  // momentum coefficients of the pulse's steps (data independent)
+  std::vector<float> beta(m + 1, 0.f);
+  {
+    double t = r.t_start;
+    for (int k = 1; k <= m; ++k) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      beta[k] = c->cfg.momentum == OFISTA_MOMENTUM_ISTA ? 0.f : static_cast<float>((t - 1.0) / tn);
+      t = tn;
+    }
+  }
+  auto u_of_step = [&](int k) {  // u_k, k = 1..m
+    return seg_ptr(c, L.seg_u, static_cast<size_t>(j) * L.rec_iters + (k - 1), vbytes);
+  };
+  int cur = 0;
+  a.u_prev = u_of_step(m);
+  a.ubar_next = ubar[cur];
+  a.cpart_next = cpart[cur];
+  a.alpha_parts = alpha_parts + static_cast<size_t>(m - 1) * L.nb;
+  OF_CK(c, launch_adj_start(a, c->st));
+  const float2 *Hn = reinterpret_cast<const float2 *>(c->base + L.seg_H + j * hbytes);
+  for (int k = m; k >= 1; --k) {
+    StepArgs sa{};
+    sa.H = Hn;
+    sa.zc = ubar[cur];
+    sa.wc = ubar[cur];
+    sa.Q = d.Q;
+    sa.items = d.items;
+    sa.tile_row0 = d.tile_row0;
+    sa.nb = L.nb;
+    sa.N = L.N;
+    sa.nitems = static_cast<int>(L.nitems);
+    sa.chunk = L.chunk;
+    OF_CK(c, launch_step_tiles(sa, c->st));
+    a.ubar_cur = ubar[cur];
+    a.cpart_cur = cpart[cur];
+    a.ubar_next = ubar[cur ^ 1];
+    a.cpart_next = cpart[cur ^ 1];
+    a.last = k == 1 ? 1 : 0;
+    a.u_prev = k >= 2 ? u_of_step(k - 1) : nullptr;
+    a.alpha_parts = k >= 2 ? alpha_parts + static_cast<size_t>(k - 2) * L.nb : nullptr;
+    a.beta_prev = k >= 2 ? beta[k - 1] : 0.f;
+    OF_CK(c, launch_adj_update(a, c->st));
+    cur ^= 1;
+  }
+  OF_CK(c, launch_adj_pulse(a, m * L.nb, L.Npad, dB, lam_out, phase_out, c->st));
+  return OFISTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ofista_status ofista_backward(ofista_ctx *c, const void *d_grad_img, double *grad_lambda,
+                              double *grad_phase) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  const Layout &L = c->L;
+  if (L.rec_every <= 0) return OFISTA_E_STATE;
+  if (!d_grad_img || !grad_lambda || !grad_phase) return OFISTA_E_ARG;
+  const int P = static_cast<int>(c->n);
+  if (P == 0 || static_cast<int>(c->rec.size()) != P) return OFISTA_E_STATE;
+  const size_t cstride = align_up(L.state_bytes);
+  char *final_ckpt = c->base + L.ckpt + static_cast<size_t>(L.n_ckpt - 1) * cstride;
+  st = export_to(c, final_ckpt);
+  if (st != OFISTA_OK) return st;
+  const std::vector<ofista_ctx::PulseRec> rec = c->rec;  // the re-runs below must not record
+  OF_CK(c, launch_image_adjoint(c->g, static_cast<const float2 *>(d_grad_img),
+                                seg_ptr(c, L.chat_bar, 0, 0), c->cfg.dict, c->cfg.haar_levels, c->st));
+  OF_CK(c, launch_fill(c->base + L.Bbar, static_cast<size_t>(L.Npad) * 2, 0u, c->st));
+  const int R = L.rec_every;
+  const int nseg = (P + R - 1) / R;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int n0 = seg * R, n1 = std::min(P, n0 + R);
+    st = import_from(c, c->base + L.ckpt + static_cast<size_t>(seg) * cstride);
+    if (st != OFISTA_OK) return st;
+    for (int n = n0; n < n1; ++n) {
+      const void *dn = c->base + L.pulses_d + static_cast<size_t>(n) * L.K * sizeof(float2);
+      st = push_impl(c, dn, rec[n].s, rec[n].phase, n - n0);
+      if (st != OFISTA_OK) return st;
+      if (rec[n].iters >= 0) {
+        st = reconstruct_impl(c, rec[n].iters, nullptr, n - n0, nullptr);
+        if (st != OFISTA_OK) return st;
+      }
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      st = reverse_pulse(c, n, n - n0);
+      if (st != OFISTA_OK) return st;
+    }
+  }
+  st = import_from(c, final_ckpt);
+  if (st != OFISTA_OK) return st;
+  c->rec = rec;
+  std::vector<double> lam(P), ph(P);
+  OF_CK(c, hipStreamSynchronize(c->st));
+  OF_CK(c, hipMemcpy(lam.data(), c->base + L.lam_dev, P * sizeof(double), hipMemcpyDeviceToHost));
+  OF_CK(c, hipMemcpy(ph.data(), c->base + L.phase_dev, P * sizeof(double), hipMemcpyDeviceToHost));
+  double gl = 0.0;
+  for (int n = 0; n < P; ++n) {
+    gl += lam[n];
+    grad_phase[n] = ph[n];
+  }
+  *grad_lambda = gl;
   return OFISTA_OK;
 }
 
@@ -574,10 +831,11 @@ ofista_status ofista_state(ofista_ctx *c, ofista_stats *out) {
   return OFISTA_OK;
 }
 
-ofista_status ofista_export_state(ofista_ctx *c, void *d_buf) {
-  ofista_status st = usable(c);
-  if (st != OFISTA_OK) return st;
-  if (!d_buf) return OFISTA_E_ARG;
+}  // extern "C"
+
+namespace {
+
+ofista_status export_to(ofista_ctx *c, void *d_buf) {
   const Layout &L = c->L;
   const int par = static_cast<int>(c->G & 1);
   double hdr[16] = {0};
@@ -608,10 +866,7 @@ ofista_status ofista_export_state(ofista_ctx *c, void *d_buf) {
   return OFISTA_OK;
 }
 
-ofista_status ofista_import_state(ofista_ctx *c, const void *d_buf) {
-  ofista_status st = usable(c);
-  if (st != OFISTA_OK) return st;
-  if (!d_buf) return OFISTA_E_ARG;
+ofista_status import_from(ofista_ctx *c, const void *d_buf) {
   const Layout &L = c->L;
   double hdr[16];
   const char *o = static_cast<const char *>(d_buf);
@@ -639,6 +894,25 @@ ofista_status ofista_import_state(ofista_ctx *c, const void *d_buf) {
   o += align_up(vec);
   OF_CK(c, hipMemcpyAsync(c->d.H, o, L.ntiles * kTile * kTile * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
   return OFISTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ofista_status ofista_export_state(ofista_ctx *c, void *d_buf) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_buf) return OFISTA_E_ARG;
+  return export_to(c, d_buf);
+}
+
+ofista_status ofista_import_state(ofista_ctx *c, const void *d_buf) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_buf) return OFISTA_E_ARG;
+  c->rec.clear();  // an imported state has no recorded history
+  return import_from(c, d_buf);
 }
 
 ofista_status ofista_profile(ofista_ctx *c, int32_t enable) {

@@ -86,6 +86,8 @@ def lib() -> ctypes.CDLL:
         "ofista_import_state": (i32, [vp, vp]),
         "ofista_profile": (i32, [vp, i32]),
         "ofista_kernel_time": (i32, [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]),
+        "ofista_backward": (i32, [vp, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
+        "ofista_set_lambda": (i32, [vp, f64]),
         "ofista_destroy": (None, [vp]),
         "ofista_error_string": (ctypes.c_char_p, [vp, i32]),
         "ofista_tile": (i32, []),
@@ -245,7 +247,8 @@ class OnlineFista:
         return int(self._lib.ofista_state_bytes(ctypes.byref(self.cfg)))
 
     def export_state(self):
-        buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        # zero-filled: the record's alignment padding is not written by the library
+        buf = torch.zeros(self.state_bytes(), dtype=torch.uint8, device=self.device)
         self._check(self._lib.ofista_export_state(self._ctx, _ptr(buf)))
         return buf
 
@@ -253,6 +256,18 @@ class OnlineFista:
         if buf.dtype != torch.uint8 or buf.numel() < self.state_bytes() or buf.device != self.device:
             raise ValueError("state buffer has the wrong type, size or device")
         self._check(self._lib.ofista_import_state(self._ctx, _ptr(buf)))
+
+    def set_lambda(self, lam: float):
+        self._check(self._lib.ofista_set_lambda(self._ctx, float(lam)))
+
+    def backward(self, grad_img: torch.Tensor):
+        """(dL/dlambda, dL/dphase per pushed pulse) for dL/dx = grad_img."""
+        self._vec(grad_img, self.N, "grad_img")
+        n = self.state()["n_pulses"]
+        gl = ctypes.c_double()
+        gp = (ctypes.c_double * max(n, 1))()
+        self._check(self._lib.ofista_backward(self._ctx, _ptr(grad_img), ctypes.byref(gl), gp))
+        return gl.value, np.array(gp[:n], dtype=np.float64)
 
     def profile(self, enable: bool):
         self._check(self._lib.ofista_profile(self._ctx, 1 if enable else 0))
@@ -274,3 +289,31 @@ class OnlineFista:
             self.close()
         except Exception:
             pass
+
+
+class OnlineFistaFn(torch.autograd.Function):
+    """x = OnlineFistaFn.apply(lam, phases, model, D, iters): the final image of
+    an online run over the pulses D[n] (positions 0..P-1) with the absolute l1
+    weight lam and per-pulse phase corrections phases[n]; differentiable in lam
+    and phases through the library's reverse pass.  `model` must be an
+    OnlineFista created with record_every > 0."""
+
+    @staticmethod
+    def forward(ctx, lam, phases, model, D, iters):
+        model.reset()
+        model.set_lambda(float(lam))
+        ph = phases.detach().cpu().double().numpy()
+        for n in range(D.shape[0]):
+            model.push_pulse(D[n], n, float(ph[n]))
+            model.reconstruct(int(iters), copy=False)
+        ctx.model = model
+        ctx.lam_dtype, ctx.ph_dtype = lam.dtype, phases.dtype
+        ctx.devices = (lam.device, phases.device)
+        return model.image()
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        gl, gp = ctx.model.backward(grad_x.contiguous().to(torch.complex64))
+        glam = torch.tensor(gl, dtype=ctx.lam_dtype, device=ctx.devices[0])
+        gph = torch.from_numpy(gp).to(dtype=ctx.ph_dtype, device=ctx.devices[1])
+        return glam, gph, None, None, None
