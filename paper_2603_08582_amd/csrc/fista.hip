@@ -62,8 +62,6 @@ __device__ double block_sum256(double v, double *red) {
   return r;
 }
 
-constexpr int kSlotBatch = 16;  // independent slot loads in flight per thread
-
 // Fixed-order sum over a wave (every lane ends with its own, lane 0 with the
 // canonical tree).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -72,100 +70,103 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Update of tile row R = blockIdx.x: sum the slots, update 64 rows.  All of
-// the workgroup's global loads (row inputs, |w|^2 parts, slots) are issued
-// before any of them is used, so the kernel waits for memory about once.
+// Update: kUpdSplit workgroups per tile row, each owning kUpdRows rows.
+// Thread (part p, row r) adds the valid slots v = p, p + kUpdParts, ... of its
+// row; slots are read kUpdBatch at a time (index clamped in range, unused
+// values replaced by zero after the load), then the parts are summed in LDS
+// in increasing p.
+constexpr int kUpdRows = kTile / kUpdSplit;  // 32
+constexpr int kUpdParts = 256 / kUpdRows;    // 8
+constexpr int kUpdBatch = 8;
+
+// Slot v of target row R: the column partials j < R come first, then the run
+// starts j = R, R + chunk, ... (row partials).
+__device__ __forceinline__ int valid_slot(int v, int R, int chunk) {
+  return v < R ? v : R + (v - R) * chunk;
+}
+
 __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
-  __shared__ float4 red4[256];
+  __shared__ float4 red[kUpdParts][kUpdRows];
   __shared__ double wred[4];
-  const int R = blockIdx.x;
-  const int nb = a.nb;
+  const int R = blockIdx.x / kUpdSplit, sub = blockIdx.x % kUpdSplit;
+  const int nb = a.nb, chunk = a.chunk, nparts = kUpdSplit * nb;
   const int t = threadIdx.x;
-  const int r = t & 63, part = t >> 6;
-  const int i = R * kTile + r;
-  const bool row_thread = t < 64;
-  const bool live = row_thread && i < a.N;
-  float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
-  if (live) {
-    z = a.zc[i];
-    cold = a.cc[i];
-    bi = a.b[i];
-    w = a.wc[i];
-  }
+  const int r = t % kUpdRows, part = t / kUpdRows;
+  const int i = R * kTile + sub * kUpdRows + r;
+  const int nvalid = R + (nb - R + chunk - 1) / chunk;
   // |w|^2 parts of the vector this step multiplied
   double m = 0.0;
-  for (int j = t; j < nb; j += 256) m += a.slot_prev[nb + j];
-  // slots written this step for row R: columns j < R (column partials) and the
-  // run starts j = R, R + chunk, ... (row partials).  Part p adds the slots
-  // j = p, p+4, p+8, ... in increasing j; loads are issued kSlotBatch at a
-  // time (j clamped in range, unused slots replaced by zero after the load).
+  for (int j = t; j < nparts; j += 256) m += a.slot_prev[nparts + j];
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 *q = a.Q + static_cast<size_t>(R) * nb * kTile + r;
-  for (int j0 = part; j0 < nb; j0 += 4 * kSlotBatch) {
-    float4 v[kSlotBatch];
+  const f32x4 *q = reinterpret_cast<const f32x4 *>(a.Q + static_cast<size_t>(R) * nb * kTile + (i - R * kTile));
+  for (int v0 = part; v0 < nvalid; v0 += kUpdParts * kUpdBatch) {
+    f32x4 x[kUpdBatch];
 #pragma unroll
-    for (int u = 0; u < kSlotBatch; ++u) {
-      const int j = j0 + 4 * u;
-      v[u] = q[static_cast<size_t>(j < nb ? j : nb - 1) * kTile];
+    for (int u = 0; u < kUpdBatch; ++u) {
+      const int v = v0 + kUpdParts * u;
+      const int j = valid_slot(v < nvalid ? v : nvalid - 1, R, chunk);
+      x[u] = __builtin_nontemporal_load(q + static_cast<size_t>(j) * kTile);
     }
 #pragma unroll
-    for (int u = 0; u < kSlotBatch; ++u) {
-      const int j = j0 + 4 * u;
-      const bool ok = j < nb && (j < R || ((j - R) % a.chunk) == 0);
-      acc.x += ok ? v[u].x : 0.f;
-      acc.y += ok ? v[u].y : 0.f;
-      acc.z += ok ? v[u].z : 0.f;
-      acc.w += ok ? v[u].w : 0.f;
+    for (int u = 0; u < kUpdBatch; ++u) {
+      const bool ok = v0 + kUpdParts * u < nvalid;
+      acc.x += ok ? x[u].x : 0.f;
+      acc.y += ok ? x[u].y : 0.f;
+      acc.z += ok ? x[u].z : 0.f;
+      acc.w += ok ? x[u].w : 0.f;
     }
   }
-  red4[t] = acc;
+  red[part][r] = acc;
   m = wave_sum(m);
   if ((t & 63) == 0) wred[t >> 6] = m;
   __syncthreads();
-  if (row_thread) {
-    const double wn2 = ((wred[0] + wred[1]) + wred[2]) + wred[3];
-    float4 s = red4[t];
+  if (t >= kUpdRows) return;
+  const double wn2 = ((wred[0] + wred[1]) + wred[2]) + wred[3];
+  float4 s = red[0][t];
 #pragma unroll
-    for (int p = 1; p < 4; ++p) {
-      const float4 v = red4[t + 64 * p];
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
+  for (int p = 1; p < kUpdParts; ++p) {
+    const float4 v = red[p][t];
+    s.x += v.x;
+    s.y += v.y;
+    s.z += v.z;
+    s.w += v.w;
+  }
+  const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
+  const float tau = static_cast<float>(a.scal->tau);
+  const float alpha = static_cast<float>(a.scal->alpha);
+  double rpart = 0.0, mpart = 0.0;
+  if (i < a.N) {
+    const float2 z = a.zc[i], cold = a.cc[i], bi = a.b[i], w = a.wc[i];
+    const float gx = s.x - bi.x, gy = s.y - bi.y;
+    const float ux = z.x - tau * gx, uy = z.y - tau * gy;
+    if (a.urec) a.urec[i] = make_float2(ux, uy);  // kept for the reverse pass
+    const float mag = sqrtf(ux * ux + uy * uy);
+    float cx = 0.f, cy = 0.f;
+    if (mag > alpha) {
+      const float f = 1.f - alpha / mag;
+      cx = ux * f;
+      cy = uy * f;
     }
-    const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
-    const float tau = static_cast<float>(a.scal->tau);
-    const float alpha = static_cast<float>(a.scal->alpha);
-    double rpart = 0.0, mpart = 0.0;
-    if (live) {
-      const float gx = s.x - bi.x, gy = s.y - bi.y;
-      const float ux = z.x - tau * gx, uy = z.y - tau * gy;
-      if (a.urec) a.urec[i] = make_float2(ux, uy);  // kept for the reverse pass
-      const float mag = sqrtf(ux * ux + uy * uy);
-      float cx = 0.f, cy = 0.f;
-      if (mag > alpha) {
-        const float f = 1.f - alpha / mag;
-        cx = ux * f;
-        cy = uy * f;
-      }
-      a.cn[i] = make_float2(cx, cy);
-      a.zn[i] = make_float2(cx + a.beta * (cx - cold.x), cy + a.beta * (cy - cold.y));
-      const float2 wnext = make_float2(s.z * inv_wn, s.w * inv_wn);
-      a.wn[i] = wnext;
-      rpart = static_cast<double>(w.x) * s.z + static_cast<double>(w.y) * s.w;
-      mpart = static_cast<double>(wnext.x) * wnext.x + static_cast<double>(wnext.y) * wnext.y;
-    } else {
-      a.cn[i] = make_float2(0.f, 0.f);
-      a.zn[i] = make_float2(0.f, 0.f);
-      a.wn[i] = make_float2(0.f, 0.f);
-    }
-    // row-block parts of Re<w, Hw> and |w'|^2, fixed order
-    rpart = wave_sum(rpart);
-    mpart = wave_sum(mpart);
-    if (t == 0) {
-      a.slot_cur[R] = rpart;
-      a.slot_cur[nb + R] = mpart;
-    }
+    a.cn[i] = make_float2(cx, cy);
+    a.zn[i] = make_float2(cx + a.beta * (cx - cold.x), cy + a.beta * (cy - cold.y));
+    const float2 wnext = make_float2(s.z * inv_wn, s.w * inv_wn);
+    a.wn[i] = wnext;
+    rpart = static_cast<double>(w.x) * s.z + static_cast<double>(w.y) * s.w;
+    mpart = static_cast<double>(wnext.x) * wnext.x + static_cast<double>(wnext.y) * wnext.y;
+  } else {
+    a.cn[i] = make_float2(0.f, 0.f);
+    a.zn[i] = make_float2(0.f, 0.f);
+    a.wn[i] = make_float2(0.f, 0.f);
+  }
+  // parts of Re<w, Hw> and |w'|^2 over this workgroup's rows, fixed order
+#pragma unroll
+  for (int off = kUpdRows / 2; off >= 1; off >>= 1) {
+    rpart += __shfl_xor(rpart, off);
+    mpart += __shfl_xor(mpart, off);
+  }
+  if (t == 0) {
+    a.slot_cur[blockIdx.x] = rpart;
+    a.slot_cur[nparts + blockIdx.x] = mpart;
   }
 }
 
@@ -199,7 +200,13 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
   auto issue = [&](float2 (&h)[kRowsPerWave], float2 &zz, float2 &ww, int jj) {
     const int J = min(J0 + jj, J1 - 1);
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) h[q] = Hrow[static_cast<size_t>(J) * kTile * kTile + q * kTile];
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      // H is streamed once per step: nontemporal loads keep it from evicting
+      // the vectors and slots from the caches
+      const f32x2 v = __builtin_nontemporal_load(
+          reinterpret_cast<const f32x2 *>(Hrow + static_cast<size_t>(J) * kTile * kTile + q * kTile));
+      h[q] = make_float2(v.x, v.y);
+    }
     zz = a.zc[J * kTile + lane];
     ww = a.wc[J * kTile + lane];
   };
@@ -250,9 +257,9 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
       v[e] = keep + __shfl_xor(send, half);
     }
   }
-  reinterpret_cast<float *>(a.Q + (static_cast<size_t>(I) * a.nb + J0) * kTile + row0)[lane] = v[0];
-
   // Column partials of the off-diagonal tiles: sum the 4 waves in fixed order.
+  // (The row partial is stored after this barrier: a store issued before it
+  // would be waited for there.)
   __syncthreads();
 #pragma unroll
   for (int jj = threadIdx.x >> 6; jj < CH; jj += 4) {
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
       a.Q[(static_cast<size_t>(J) * a.nb + I) * kTile + lane] = s;
     }
   }
-
+  reinterpret_cast<float *>(a.Q + (static_cast<size_t>(I) * a.nb + J0) * kTile + row0)[lane] = v[0];
 }
 
 // Per-pulse scalars: lambda (first pulse), sigma^2 of position s, rho_{n-1}
@@ -279,14 +286,14 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
 __global__ __launch_bounds__(256) void k_scalars(DevScalars *scal, const double *sig2, int s,
                                                  int first, int rel, double lam_in, int lip,
                                                  int have_rho, const double *slot_r,
-                                                 const double *slot_m, int nb) {
+                                                 const double *slot_m, int nparts) {
   __shared__ double red[256];
   double rho = 0.0;
   if (have_rho) {
     double pr = 0.0, pm = 0.0;
-    for (int j = threadIdx.x; j < nb; j += 256) {
+    for (int j = threadIdx.x; j < nparts; j += 256) {
       pr += slot_r[j];
-      pm += slot_m[nb + j];
+      pm += slot_m[nparts + j];
     }
     const double rs = block_sum256(pr, red);
     const double ms = block_sum256(pm, red);
@@ -312,11 +319,11 @@ __global__ void k_fill(unsigned *p, size_t n, unsigned value) {
 }
 
 // w_0 = 1/sqrt(N) on the real pixels; slot0 says |w_0|^2 = 1.
-__global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nb) {
+__global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nparts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Npad) w[i] = make_float2(i < N ? static_cast<float>(1.0 / sqrt(static_cast<double>(N))) : 0.f, 0.f);
-  if (i < 2 * nb) {
-    slot0[i] = (i == nb) ? 1.0 : 0.0;
+  if (i < 2 * nparts) {
+    slot0[i] = (i == nparts) ? 1.0 : 0.0;
     slot1[i] = 0.0;
   }
 }
@@ -324,8 +331,8 @@ __global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int
 }  // namespace
 
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st) {
-  if (a.chunk == 8)
-    hipLaunchKernelGGL(k_step_tiles<8>, dim3(a.nitems), dim3(256), 0, st, a);
+  if (a.chunk == 2)
+    hipLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, a);
   else if (a.chunk == 4)
     hipLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, a);
   else
@@ -334,15 +341,15 @@ hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_step_update(const StepArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_update, dim3(a.nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
                           double lam_in, int lip, int have_rho, const double *slot_r,
-                          const double *slot_m, int nb, hipStream_t st) {
+                          const double *slot_m, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, st, scal, sig2, s, first, rel, lam_in,
-                     lip, have_rho, slot_r, slot_m, nb);
+                     lip, have_rho, slot_r, slot_m, nparts);
   return hipGetLastError();
 }
 
@@ -355,11 +362,11 @@ hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nb,
+hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N, int Npad, int nparts,
                              hipStream_t st) {
-  const int n = Npad > 2 * nb ? Npad : 2 * nb;
+  const int n = Npad > 2 * nparts ? Npad : 2 * nparts;
   hipLaunchKernelGGL(k_init_power, dim3((n + 255) / 256), dim3(256), 0, st, w, slot0, slot1, N,
-                     Npad, nb);
+                     Npad, nparts);
   return hipGetLastError();
 }
 

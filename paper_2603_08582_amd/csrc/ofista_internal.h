@@ -9,13 +9,20 @@
 
 namespace ofista {
 
+// Vector types for nontemporal loads (the builtin takes scalar or
+// ext_vector_type pointers only).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Edge of the square tiles of the packed Hermitian storage.  H is kept as
 // the nb(nb+1)/2 tiles (I, J), I <= J, of a zero-padded Npad x Npad matrix
 // (Npad = nb * kTile), each tile row-major, tiles in row-major upper order.
 constexpr int kTile = 64;
-// Tiles per FISTA work item (a run of tiles along one tile row): 4 or 8.
-constexpr int kChunkSmall = 4;
-constexpr int kChunkLarge = 8;
+// Tiles per FISTA work item (a run of tiles along one tile row): 2 or 4.
+constexpr int kChunk = 2;
+// Workgroups per tile row in the FISTA update; the power-iteration parts
+// (slots) are kept per update workgroup: nparts = kUpdSplit * nb.
+constexpr int kUpdSplit = 2;
 // Frequencies staged per LDS step of the Gram update.
 constexpr int kGramKB = 32;
 
@@ -59,7 +66,7 @@ struct DevState {
   float2 *zbuf[2];   // momentum point z
   float2 *wbuf[2];   // power vector
   float4 *Q;         // matvec partials, nb x nb x kTile of (yz, yw)
-  double *slots[2];  // per tile row: [0, nb) Re<w, Hw> parts, [nb, 2nb) |w'|^2 parts
+  double *slots[2];  // per update workgroup: [0, P) Re<w, Hw> parts, [P, 2P) |w'|^2 parts, P = nparts
   DevScalars *scal;
   double *pos;       // npos x 3
   double *sig2;      // npos, ||A_s||_2^2 per position
@@ -140,7 +147,7 @@ hipError_t launch_step_update(const StepArgs &a, hipStream_t st);
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
                           int first, int rel, double lam_in, int lip,
                           int have_rho, const double *slot_r,
-                          const double *slot_m, int nb, hipStream_t st);
+                          const double *slot_m, int nparts, hipStream_t st);
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
 hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N,
                              int Npad, int nb, hipStream_t st);

@@ -22,7 +22,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int N = 0, Npad = 0, nb = 0, K = 0, npos = 0, chunk = 4;
+  int N = 0, Npad = 0, nb = 0, K = 0, npos = 0, chunk = 4, nparts = 0;
   size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
@@ -38,7 +38,7 @@ struct Layout {
 
 size_t state_record_bytes(const Layout &L) {
   return align_up(16 * sizeof(double)) + align_up(sizeof(DevScalars)) +
-         2 * align_up(2 * L.nb * sizeof(double)) +
+         2 * align_up(2 * L.nparts * sizeof(double)) +
          3 * align_up(static_cast<size_t>(L.Npad) * sizeof(float2)) +
          L.ntiles * kTile * kTile * sizeof(float2);
 }
@@ -49,9 +49,9 @@ size_t count_items(int nb, int chunk) {
   return n;
 }
 
-// Run length of the FISTA work items.  Runs of 4 tiles measured faster than
-// runs of 8 at both N = 4096 and N = 16384 (more workgroups in flight).
-int pick_chunk(int) { return kChunkSmall; }
+// Run length of the FISTA work items.  Runs of 2 tiles measured faster than
+// runs of 4 or 8 at both N = 4096 and N = 16384 (more workgroups in flight).
+int pick_chunk(int) { return kChunk; }
 
 ofista_status check(const ofista_config *c, std::string *why) {
   auto bad = [&](const char *m) {
@@ -110,6 +110,7 @@ Layout layout(const ofista_config *c) {
   L.ntiles = static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
   L.ntiles_grid = (L.ntiles + 7) / 8 * 8;
   L.chunk = pick_chunk(L.nb);
+  L.nparts = kUpdSplit * L.nb;
   L.nitems = count_items(L.nb, L.chunk);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -128,8 +129,8 @@ Layout layout(const ofista_config *c) {
   L.w0 = take(vec);
   L.w1 = take(vec);
   L.Q = take(static_cast<size_t>(L.nb) * L.nb * kTile * sizeof(float4));
-  L.slot0 = take(2 * L.nb * sizeof(double));
-  L.slot1 = take(2 * L.nb * sizeof(double));
+  L.slot0 = take(2 * L.nparts * sizeof(double));
+  L.slot1 = take(2 * L.nparts * sizeof(double));
   L.scal = take(sizeof(DevScalars));
   L.pos = take(3 * static_cast<size_t>(L.npos) * sizeof(double));
   L.sig2 = take(L.npos * sizeof(double));
@@ -290,7 +291,7 @@ ofista_status do_reset(ofista_ctx *c) {
   }
   OF_CK(c, launch_fill(d.wbuf[1], vecw, 0u, c->st));
   OF_CK(c, launch_fill(d.scal, sizeof(DevScalars) / 4, 0u, c->st));
-  OF_CK(c, launch_init_power(d.wbuf[0], d.slots[0], d.slots[1], L.N, L.Npad, L.nb, c->st));
+  OF_CK(c, launch_init_power(d.wbuf[0], d.slots[0], d.slots[1], L.N, L.Npad, L.nparts, c->st));
   c->n = 0;
   c->G = 0;
   c->have_iter = false;
@@ -477,7 +478,7 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
     const int par = static_cast<int>(c->G & 1);
     OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
                             c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
-                            L.nb, c->st));
+                            L.nparts, c->st));
   }
   if (seg_j >= 0) {
     const size_t hbytes = L.ntiles * kTile * kTile * sizeof(float2);
@@ -804,19 +805,19 @@ ofista_status ofista_state(ofista_ctx *c, ofista_stats *out) {
   if (st != OFISTA_OK) return st;
   if (!out) return OFISTA_E_ARG;
   DevScalars s{};
-  const int nb = c->L.nb;
-  std::vector<double> sr(2 * nb), sm(2 * nb);
+  const int np = c->L.nparts;
+  std::vector<double> sr(2 * np), sm(2 * np);
   const int par = static_cast<int>(c->G & 1);
   OF_CK(c, hipStreamSynchronize(c->st));
   OF_CK(c, hipMemcpy(&s, c->d.scal, sizeof(s), hipMemcpyDeviceToHost));
-  OF_CK(c, hipMemcpy(sr.data(), c->d.slots[par], 2 * nb * sizeof(double), hipMemcpyDeviceToHost));
-  OF_CK(c, hipMemcpy(sm.data(), c->d.slots[par ^ 1], 2 * nb * sizeof(double), hipMemcpyDeviceToHost));
+  OF_CK(c, hipMemcpy(sr.data(), c->d.slots[par], 2 * np * sizeof(double), hipMemcpyDeviceToHost));
+  OF_CK(c, hipMemcpy(sm.data(), c->d.slots[par ^ 1], 2 * np * sizeof(double), hipMemcpyDeviceToHost));
   double rho = 0.0;
   if (c->have_iter) {
     double rs = 0.0, ms = 0.0;
-    for (int j = 0; j < nb; ++j) {
+    for (int j = 0; j < np; ++j) {
       rs += sr[j];
-      ms += sm[nb + j];
+      ms += sm[np + j];
     }
     rho = rs / ms;
   }
@@ -851,10 +852,10 @@ ofista_status export_to(ofista_ctx *c, void *d_buf) {
   o += align_up(sizeof(hdr));
   OF_CK(c, hipMemcpyAsync(o, c->d.scal, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->st));
   o += align_up(sizeof(DevScalars));
-  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par], 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  o += align_up(2 * L.nb * sizeof(double));
-  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par ^ 1], 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par], 2 * L.nparts * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nparts * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(o, c->d.slots[par ^ 1], 2 * L.nparts * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nparts * sizeof(double));
   OF_CK(c, hipMemcpyAsync(o, c->d.wbuf[par], vec, hipMemcpyDeviceToDevice, c->st));
   o += align_up(vec);
   OF_CK(c, hipMemcpyAsync(o, c->d.cbuf[par], vec, hipMemcpyDeviceToDevice, c->st));
@@ -882,10 +883,10 @@ ofista_status import_from(ofista_ctx *c, const void *d_buf) {
   o += align_up(sizeof(hdr));
   OF_CK(c, hipMemcpyAsync(c->d.scal, o, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->st));
   o += align_up(sizeof(DevScalars));
-  OF_CK(c, hipMemcpyAsync(c->d.slots[par], o, 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  o += align_up(2 * L.nb * sizeof(double));
-  OF_CK(c, hipMemcpyAsync(c->d.slots[par ^ 1], o, 2 * L.nb * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  o += align_up(2 * L.nb * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(c->d.slots[par], o, 2 * L.nparts * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nparts * sizeof(double));
+  OF_CK(c, hipMemcpyAsync(c->d.slots[par ^ 1], o, 2 * L.nparts * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(2 * L.nparts * sizeof(double));
   OF_CK(c, hipMemcpyAsync(c->d.wbuf[par], o, vec, hipMemcpyDeviceToDevice, c->st));
   o += align_up(vec);
   OF_CK(c, hipMemcpyAsync(c->d.cbuf[par], o, vec, hipMemcpyDeviceToDevice, c->st));
