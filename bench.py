@@ -165,7 +165,7 @@ def main():
                    "launches": gram_n}
     rl_step = {"bound": "hbm", "achieved": step_bytes / (step_avg * 1e-3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step"),
-               "kernel": "k_fista_step", "avg_ms": step_avg, "launches": step_n}
+               "kernel": "k_step_tiles", "avg_ms": step_avg, "launches": step_n}
     for r in (rl_gram, rl_step):
         r["frac"] = r["achieved"] / r["peak"]
     dominant, other = (rl_step, rl_gram) if step_ms >= gram_ms else (rl_gram, rl_step)

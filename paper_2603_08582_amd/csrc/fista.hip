@@ -330,18 +330,28 @@ __global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int
 
 }  // namespace
 
-hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st) {
-  if (a.chunk == 2)
-    hipLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, a);
-  else if (a.chunk == 4)
-    hipLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, a);
-  else
+hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (a.chunk == 2) {
+    if (t0)
+      hipExtLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
+    else
+      hipLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, a);
+  } else if (a.chunk == 4) {
+    if (t0)
+      hipExtLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
+    else
+      hipLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, a);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step_update(const StepArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
+hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, t0, t1, 0, a);
+  else
+    hipLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -467,10 +467,14 @@ __global__ __launch_bounds__(256) void k_gram_entries(int n, int N, const float2
 
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (g.K > kMaxFreq) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
-                     ntiles_grid, A, tile_ij, H, corr);
+  if (t0)
+    hipExtLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, t0, t1, 0,
+                          g.K, g.Npad, ntiles_grid, A, tile_ij, H, corr);
+  else
+    hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
+                       ntiles_grid, A, tile_ij, H, corr);
   return hipGetLastError();
 }
 
@@ -484,12 +488,18 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
 }
 
 hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
-                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st) {
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st,
+                              hipEvent_t t0, hipEvent_t t1) {
   if (g.K % kBfKB != 0) return hipErrorInvalidValue;
   dim3 sgrid(g.Npad / kSplitTile, (g.K + kSplitTile - 1) / kSplitTile);
   hipLaunchKernelGGL(k_split_bf16, sgrid, dim3(256), 0, st, g.K, g.Npad, A, Ahi, Alo);
-  hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad, ntiles_grid,
-                     Ahi, Alo, tile_ij, H);
+  if (t0)  // the events time the product kernel only
+    hipExtLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles_grid), dim3(256), 0, st, t0, t1, 0, g.K,
+                          g.Npad, ntiles_grid, static_cast<const unsigned *>(Ahi),
+                          static_cast<const unsigned *>(Alo), tile_ij, H);
+  else
+    hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad, ntiles_grid,
+                       Ahi, Alo, tile_ij, H);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -103,8 +104,11 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
                        int first, hipStream_t st, float2 *delta = nullptr);
 // Split-BF16 Gram update (K must be a multiple of 32): split A into the
 // pixel-major hi/lo planes, then H += A^H A from three BF16 products.
+// Launchers of the timed kernels take optional events (t0, t1): when given,
+// they bracket that one kernel's execution (hipExtLaunchKernelGGL).
 hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
-                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st);
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st,
+                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Correlation fused into the Gram update: b += A^H (d e^{-i phi}).
 struct CorrArgs {
   const float2 *d;
@@ -115,7 +119,7 @@ struct CorrArgs {
 };
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            hipStream_t st);
+                            hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
                                const int *ii, const int *jj, float2 *out, hipStream_t st);
 hipError_t launch_gram_dense(const Geom &g, const float2 *H,
@@ -142,8 +146,10 @@ struct StepArgs {
   int nb, N, nitems, chunk;
   float beta;
 };
-hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st);
-hipError_t launch_step_update(const StepArgs &a, hipStream_t st);
+hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,
+                             hipEvent_t t1 = nullptr);
+hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,
+                              hipEvent_t t1 = nullptr);
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
                           int first, int rel, double lam_in, int lip,
                           int have_rho, const double *slot_r,

@@ -260,20 +260,27 @@ hipEvent_t take_event(ofista_ctx *c) {
 }
 
 // Bracket one launch with events when profiling.
+// Events around one launch when profiling.  A scope made with attach = true
+// records nothing itself: its events go to the launcher, which has the
+// runtime stamp them at the start and end of that kernel (t0(), t1()).
 struct ProfScope {
   ofista_ctx *c;
   int cls;
+  bool attach;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(ofista_ctx *ctx, int k) : c(ctx), cls(k) {
+  ProfScope(ofista_ctx *ctx, int k, bool attach_to_kernel = false)
+      : c(ctx), cls(k), attach(attach_to_kernel) {
     if (c->prof) {
       a = take_event(c);
       b = take_event(c);
-      if (a && b) hipEventRecord(a, c->st);
+      if (a && b && !attach) hipEventRecord(a, c->st);
     }
   }
+  hipEvent_t t0() const { return a && b ? a : nullptr; }
+  hipEvent_t t1() const { return a && b ? b : nullptr; }
   ~ProfScope() {
     if (c->prof && a && b) {
-      hipEventRecord(b, c->st);
+      if (!attach) hipEventRecord(b, c->st);
       c->ev.push_back({cls, {a, b}});
     }
   }
@@ -463,15 +470,15 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
       OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
                            std::sin(phase_corr), d.b, d.scal, first, c->st));
     }
-    ProfScope p(c, kProfGram);
+    ProfScope p(c, kProfGram, true);
     OF_CK(c, launch_gram_bf16x3(c->g, d.A, d.Ahi, d.Alo, d.H, d.tile_ij,
-                                static_cast<int>(L.ntiles_grid), c->st));
+                                static_cast<int>(L.ntiles_grid), c->st, p.t0(), p.t1()));
   } else {
-    ProfScope p(c, kProfGram);
+    ProfScope p(c, kProfGram, true);
     CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
     OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.ntiles_grid), corr,
-                              c->st));
+                              c->st, p.t0(), p.t1()));
   }
   {
     ProfScope p(c, kProfScalars);
@@ -526,12 +533,12 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.chunk = L.chunk;
     a.beta = static_cast<float>(beta);
     {
-      ProfScope ps(c, kProfStep);
-      OF_CK(c, launch_step_tiles(a, c->st));
+      ProfScope ps(c, kProfStep, true);
+      OF_CK(c, launch_step_tiles(a, c->st, ps.t0(), ps.t1()));
     }
     {
-      ProfScope ps(c, kProfUpdate);
-      OF_CK(c, launch_step_update(a, c->st));
+      ProfScope ps(c, kProfUpdate, true);
+      OF_CK(c, launch_step_update(a, c->st, ps.t0(), ps.t1()));
     }
     c->G += 1;
     t = tn;
