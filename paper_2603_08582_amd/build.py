@@ -24,6 +24,10 @@ BUILD = HERE.parent / "_build" / "ofista"
 
 ARCH = os.environ.get("OFISTA_ARCH", "gfx950")
 SOURCES = ["rows.hip", "gram.hip", "fista.hip", "adjoint.hip", "runtime.cpp"]
+# Per-source extra flags.  The Gram kernels keep their MFMA accumulators in
+# ordinary VGPRs (no copies to and from the accumulation registers around
+# each LDS stage): same results bit for bit, fewer registers, higher occupancy.
+EXTRA = {"gram.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -43,7 +47,7 @@ def _flags():
 def _compile(src: str) -> Path:
     BUILD.mkdir(parents=True, exist_ok=True)
     obj = BUILD / (src + ".o")
-    cmd = [hipcc(), *_flags(), "-c", str(CSRC / src), "-o", str(obj)]
+    cmd = [hipcc(), *_flags(), *EXTRA.get(src, []), "-c", str(CSRC / src), "-o", str(obj)]
     if src.endswith(".cpp"):
         cmd.insert(1, "-x")
         cmd.insert(2, "hip")
