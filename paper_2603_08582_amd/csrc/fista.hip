@@ -94,6 +94,15 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   const int r = t % kUpdRows, part = t / kUpdRows;
   const int i = R * kTile + sub * kUpdRows + r;
   const int nvalid = R + (nb - R + chunk - 1) / chunk;
+  // this row's inputs, loaded before the slots so both arrive together
+  const bool live = t < kUpdRows && i < a.N;
+  float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
+  if (live) {
+    z = a.zc[i];
+    cold = a.cc[i];
+    bi = a.b[i];
+    w = a.wc[i];
+  }
   // |w|^2 parts of the vector this step multiplied
   double m = 0.0;
   for (int j = t; j < nparts; j += 256) m += a.slot_prev[nparts + j];
@@ -135,8 +144,7 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   const float tau = static_cast<float>(a.scal->tau);
   const float alpha = static_cast<float>(a.scal->alpha);
   double rpart = 0.0, mpart = 0.0;
-  if (i < a.N) {
-    const float2 z = a.zc[i], cold = a.cc[i], bi = a.b[i], w = a.wc[i];
+  if (live) {
     const float gx = s.x - bi.x, gy = s.y - bi.y;
     const float ux = z.x - tau * gx, uy = z.y - tau * gy;
     if (a.urec) a.urec[i] = make_float2(ux, uy);  // kept for the reverse pass

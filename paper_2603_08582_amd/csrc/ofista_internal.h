@@ -25,7 +25,7 @@ constexpr int kChunk = 2;
 // (slots) are kept per update workgroup: nparts = kUpdSplit * nb.
 constexpr int kUpdSplit = 2;
 // Frequencies staged per LDS step of the Gram update.
-constexpr int kGramKB = 32;
+constexpr int kGramKB = 16;
 
 // Largest number of frequencies per pulse.
 constexpr int kMaxFreq = 1024;
