@@ -92,20 +92,22 @@ class OnlineFistaOracle:
     """Online FISTA state machine in complex128 (one object per image).
 
     pixel_xyz: (N, 3) pixel centres; positions: (P_pos, 3) platform positions;
-    freqs: (K,) Hz; dictionary: "identity" or "haar" (with n_side, levels).
+    freqs: (K,) Hz; dictionary: "identity", "haar" (with n_side, levels) or
+    "edgelet" (with n_side, edge_lengths, edge_rotations in degrees); the
+    coefficient count M is the dictionary's column count.
     """
 
     def __init__(self, pixel_xyz, positions, freqs, dictionary="identity",
                  n_side=None, levels=0, lam=None, lam_rel=0.05, lip="running",
-                 momentum="fista", kernel_sign=-1):
+                 momentum="fista", kernel_sign=-1, edge_lengths=(), edge_rotations=()):
         self.pixel_xyz = np.asarray(pixel_xyz, np.float64)
         self.positions = np.asarray(positions, np.float64)
         self.freqs = np.asarray(freqs, np.float64)
         N = self.pixel_xyz.shape[0]
         if n_side is None:
             n_side = int(round(math.sqrt(N)))
-        self.W = synthesis_matrix(dictionary, n_side, levels)
-        self.M = N
+        self.W = synthesis_matrix(dictionary, n_side, levels, edge_lengths, edge_rotations)
+        self.M = N if self.W is None else self.W.shape[1]
         self.lam_abs = lam
         self.lam_rel = lam_rel
         self.lip = lip
@@ -118,6 +120,8 @@ class OnlineFistaOracle:
     def from_workload(cls, wl, **kw):
         s = wl.spec
         kw.setdefault("lam_rel", s.lambda_rel)
+        kw.setdefault("edge_lengths", s.edge_lengths)
+        kw.setdefault("edge_rotations", s.edge_rotations_deg)
         return cls(wl.pixel_xyz(), wl.positions, wl.freqs(), s.dictionary,
                    s.n_side, s.haar_levels, **kw)
 

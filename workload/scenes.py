@@ -9,6 +9,8 @@ m inner steps per pulse) at the sizes of the five benchmark configurations:
   ``autofocus``  64x64 pixels,   64 pulses over 20 deg,  K=256,  identity, phase errors
   ``large``     128x128 pixels, 256 pulses over 30 deg,  K=512,  identity, 40 dB range
   ``xlarge``    256x256 pixels, 512 pulses over 40 deg,  K=1024, identity, split-BF16
+  ``edgelet64``  64x64 pixels,  128 pulses over 20 deg,  K=256,  edgelets (length 4,
+                 0 and 90 deg), scene of axis-aligned segments
 
 Readings of details the paper leaves open (all listed in the design doc):
 
@@ -22,6 +24,9 @@ Readings of details the paper leaves open (all listed in the design doc):
 * a line target is sampled every pixel spacing along its length, each sample is
   snapped to the nearest pixel centre (duplicates removed) and the whole line
   carries one complex reflectivity; overlapping targets add;
+* a segment target is an axis-aligned run of pixels (horizontal or vertical
+  with probability 1/2, length drawn from ``segment_px``, start uniform among
+  the positions that keep it on the grid) carrying one complex reflectivity;
 * noise draws are unit-variance circular complex normals (Re, Im ~ N(0, 1/2));
   the consumer scales them to the stated SNR per pulse.
 
@@ -52,8 +57,12 @@ class WorkloadSpec:
     n_lines: int = 0
     line_len_m: tuple = (5.0, 10.0)
     magnitude: str = "uniform"  # "uniform": |rho| ~ U[0.5, 1]; "log40": 10**U(-2, 0)
-    dictionary: str = "identity"  # "identity" | "haar"
+    dictionary: str = "identity"  # "identity" | "haar" | "edgelet"
     haar_levels: int = 0
+    edge_lengths: tuple = ()        # edgelet lengths in pixels
+    edge_rotations_deg: tuple = ()  # edgelet rotations, degrees
+    n_segments: int = 0             # axis-aligned segment targets
+    segment_px: tuple = (4, 8)      # their lengths, pixels
     snr_db: float = 30.0
     inner_steps: int = 20       # m of Algorithm 1
     phase_error_rad: float = 0.0  # per-pulse phase errors U[-e, e] (0 = none)
@@ -92,6 +101,11 @@ CONFIGS = {
         name="xlarge", n_side=256, patch_m=250.0, n_pulses=512, azimuth_deg=40.0,
         n_freq=1024, f_lo=9.7e9, f_hi=10.3e9, n_points=1000, n_lines=20,
         snr_db=30.0, inner_steps=10, precision="split_bf16", seed=2607),
+    "edgelet64": WorkloadSpec(
+        name="edgelet64", n_side=64, patch_m=60.0, n_pulses=128, azimuth_deg=20.0,
+        n_freq=256, f_lo=9.8e9, f_hi=10.2e9, n_points=0, n_segments=8,
+        dictionary="edgelet", edge_lengths=(4,), edge_rotations_deg=(0.0, 90.0),
+        snr_db=30.0, inner_steps=20, seed=2608),
 }
 
 
@@ -144,8 +158,8 @@ def _draw_magnitudes(rng, kind: str, size: int) -> np.ndarray:
 
 def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
     """Draw one workload.  All draws come from one PCG64 stream in a fixed order:
-    point pixels, point magnitudes, point phases, line parameters, noise,
-    phase errors."""
+    point pixels, point magnitudes, point phases, line parameters, segment
+    parameters, noise, phase errors."""
     if isinstance(s, str):
         s = CONFIGS[s]
     rng = np.random.Generator(np.random.PCG64(s.seed if seed is None else seed))
@@ -180,6 +194,21 @@ def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
             idx = np.unique(iy * n + ix)
             rho[idx] += lmag[j] * np.exp(1j * lph[j])
 
+    if s.n_segments:
+        horiz = rng.random(s.n_segments) < 0.5
+        seg_len = rng.choice(np.asarray(s.segment_px), size=s.n_segments)
+        start_u = rng.random(s.n_segments)
+        start_v = rng.random(s.n_segments)
+        smag = _draw_magnitudes(rng, s.magnitude, s.n_segments)
+        sph = rng.uniform(0.0, 2 * math.pi, s.n_segments)
+        for j in range(s.n_segments):
+            ln = int(seg_len[j])
+            a = int(start_u[j] * (n - ln + 1))   # along the segment
+            b = int(start_v[j] * n)              # across it
+            run = a + np.arange(ln)
+            idx = b * n + run if horiz[j] else run * n + b
+            rho[idx] += smag[j] * np.exp(1j * sph[j])
+
     g = rng.standard_normal((P, K, 2))
     noise = (g[..., 0] + 1j * g[..., 1]) / math.sqrt(2.0)
 
@@ -205,6 +234,7 @@ def library_kwargs(wl: Workload, **overrides) -> dict:
     kw = dict(n_x=s.n_side, n_y=s.n_side, x0=wl.x0, y0=wl.y0, dx=wl.dx, dy=wl.dy,
               positions=wl.positions, freq0=wl.freq0, dfreq=wl.dfreq, n_freq=s.n_freq,
               dictionary=s.dictionary, haar_levels=s.haar_levels, lam=s.lambda_rel,
-              lam_relative=True, precision=s.precision)
+              lam_relative=True, precision=s.precision,
+              edge_lengths=tuple(s.edge_lengths), edge_rotations=tuple(s.edge_rotations_deg))
     kw.update(overrides)
     return kw
