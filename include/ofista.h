@@ -15,7 +15,10 @@
  * - Complex values are complex64: two consecutive floats (re, im).
  * - Pixels form an n_x by n_y grid on the plane z = 0; pixel (iy, ix) sits at
  *   (x0 + ix*dx, y0 + iy*dy, 0) and has flat index i = iy*n_x + ix; N = n_x*n_y.
- *   Coefficients use the same flat index (M = N for both dictionaries).
+ * - The sparse coefficients c (length M) are the dictionary's: M = N with the
+ *   same flat index for IDENTITY and HAAR2D; M is the atom count for EDGELET
+ *   (ofista_coef_count).  H is M x M, b and every coefficient vector have M
+ *   entries; images and scenes have N.
  * - The kernel of F_s is exp(-i 4 pi f_k R_{s,i} / c0) with R the Euclidean
  *   distance between platform position s and pixel i and f_k = freq0 + k*dfreq
  *   (the Section II phase with amplitude 1, on a stepped-frequency grid).
@@ -50,7 +53,21 @@ typedef enum ofista_status {
   OFISTA_E_HIP = -6          /* a HIP runtime call failed (ctx poisoned)     */
 } ofista_status;
 
-enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1 };
+/* Dictionaries W (the paper's H of Section III-A, N x M, real):
+   IDENTITY: W = I.
+   HAAR2D: orthonormal separable 2-D Haar basis, haar_levels levels, nested
+     (Mallat) coefficient layout.
+   EDGELET: the over-complete binary edgelets of Section III-A on a square grid
+     (n = n_x = n_y).  An atom is a rotation psi (degrees, from
+     edge_rotations_deg, converted with the constant pi/180), a length l in
+     pixels (from edge_lengths, 1 <= l <= n-1) and an integer centre (x0, y0)
+     (x = column, y = row).  Its pixels are the distinct roundings of
+     (x0 + u cos psi, y0 + u sin psi), u = t - (l-1)/2, t = 0 .. l-1, each
+     coordinate rounded as floor(v + 0.5 - 1e-9) (nearest, ties down); atoms
+     with a pixel off the grid are dropped.  W[p, m] = 1 on the pixels of atom
+     m.  Atoms are ordered by rotation, then length (as listed), then centre
+     row, then centre column. */
+enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1, OFISTA_DICT_EDGELET = 2 };
 /* Arithmetic of the Gram update: FP32 MFMA, or BF16 MFMA on a hi+lo split of
    each operand (three products, FP32 accumulation; needs n_freq divisible by
    32, else OFISTA_E_UNSUPPORTED). */
@@ -90,6 +107,10 @@ typedef struct ofista_config {
   int32_t max_pulses;      /* pulses that can be recorded (record_every > 0) */
   int32_t max_iters;       /* inner steps per reconstruct that can be
                               recorded (record_every > 0)                    */
+  int32_t n_edge_lengths;  /* EDGELET: number of lengths (>= 1)               */
+  const int32_t *edge_lengths;      /* host, copied during ofista_create      */
+  int32_t n_edge_rotations;         /* EDGELET: number of rotations (>= 1)    */
+  const double *edge_rotations_deg; /* host, degrees, copied                  */
 } ofista_config;
 
 typedef struct ofista_stats {
@@ -114,11 +135,17 @@ size_t ofista_workspace_bytes(const ofista_config *cfg);
    accept it (workspace aside). */
 ofista_status ofista_check_config(const ofista_config *cfg);
 
+/* M, the number of coefficients (dictionary atoms) for cfg; -1 when cfg is
+   invalid.  Pure host function. */
+int64_t ofista_coef_count(const ofista_config *cfg);
+
 /* init(scene, geometry, lambda).  Validates cfg, carves the caller-owned
    workspace (device memory of at least ofista_workspace_bytes(cfg) bytes,
    256-byte aligned, kept alive by the caller until ofista_destroy), copies the
    host tables, precomputes ||A_s||_2^2 for every position (it depends only on
-   the geometry) and zeroes the state.  hip_stream is a hipStream_t (NULL =
+   the geometry; for EDGELET by forming A_s A_s^H per position in FP64, using
+   the H region of the workspace as scratch, OFISTA_E_UNSUPPORTED if
+   K*K*16 bytes exceed that region) and zeroes the state.  hip_stream is a hipStream_t (NULL =
    the null stream).  The ctx (host memory) is owned by the library. */
 ofista_status ofista_create(const ofista_config *cfg, void *d_workspace,
                             size_t workspace_bytes, void *hip_stream,
@@ -137,7 +164,7 @@ ofista_status ofista_push_pulse(struct ofista_ctx *ctx, const void *d_pulse,
 
 /* reconstruct(iters): Algorithm 1 with iters inner steps on the current
    (H_n, b_n), warm-started from c_hat_{n-1} and t_{n-1}.  iters may be 0.
-   d_coef_out: device, N complex64, receives c_hat_n (NULL = not copied).
+   d_coef_out: device, M complex64, receives c_hat_n (NULL = not copied).
    OFISTA_E_STATE before the first pulse. */
 ofista_status ofista_reconstruct(struct ofista_ctx *ctx, int32_t iters,
                                  void *d_coef_out);
@@ -159,14 +186,15 @@ ofista_status ofista_echo(struct ofista_ctx *ctx, int32_t s, const void *d_rho,
                           const void *d_noise, double snr_db, double phase_err,
                           void *d_out);
 
-/* Inspection.  ofista_rows: A_s for position s into d_out (K x N complex64,
+/* Inspection.  ofista_rows: A_s for position s into d_out (K x M complex64,
    row k contiguous).  ofista_gram: the Hermitian H_n expanded to a dense
-   N x N complex64 matrix (row-major; N <= 16384, else OFISTA_E_UNSUPPORTED).  ofista_vector: which = 0 b, 1 c_hat,
-   2 power vector w (unnormalised), N complex64 each. */
+   M x M complex64 matrix (row-major; M <= 16384, else OFISTA_E_UNSUPPORTED).
+   ofista_vector: which = 0 b, 1 c_hat, 2 power vector w (unnormalised), M
+   complex64 each. */
 ofista_status ofista_rows(struct ofista_ctx *ctx, int32_t s, void *d_out);
 /* Sampled entries out[t] = H_n[i[t], j[t]] for t < n, read from the packed
-   storage at any N.  d_i, d_j: device int32 arrays of n pixel indices;
-   d_out: device, n complex64.  Indices outside [0, N) give NaN. */
+   storage at any M.  d_i, d_j: device int32 arrays of n coefficient indices;
+   d_out: device, n complex64.  Indices outside [0, M) give NaN. */
 ofista_status ofista_gram_entries(struct ofista_ctx *ctx, int32_t n, const int32_t *d_i,
                                   const int32_t *d_j, void *d_out);
 ofista_status ofista_gram(struct ofista_ctx *ctx, void *d_out);

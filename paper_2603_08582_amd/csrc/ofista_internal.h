@@ -46,11 +46,26 @@ struct DevScalars {
   double pad1[2];
 };
 
-// Geometry passed by value.
+// Geometry passed by value.  N is the coefficient count M (the length of b,
+// c and every FISTA vector; Npad = M rounded up to kTile), npix = nx*ny the
+// pixel count (N == npix except for the edgelet dictionary).
 struct Geom {
-  int nx, ny, N, Npad, K, npos;
+  int nx, ny, N, Npad, K, npos, npix;
   double x0, y0, dx, dy;
   double f0, df;
+};
+
+// Dictionary of the forward rows and the image.  Edgelet atoms are stored
+// twice as compressed index lists: atom -> pixels and pixel -> atoms (both in
+// increasing order), so that A = F W and x = W c are gathers with a fixed
+// summation order.
+struct DictTabs {
+  int kind;              // OFISTA_DICT_* value
+  int levels;            // Haar levels
+  const int *atom_ptr;   // M + 1 offsets into atom_pix
+  const int *atom_pix;
+  const int *pix_ptr;    // npix + 1 offsets into pix_atom
+  const int *pix_atom;
 };
 
 // One FISTA work item: tile row I, tiles J0 .. J1-1 (J0 >= I).
@@ -75,6 +90,7 @@ struct DevState {
   int2 *tile_ij;     // logical tile -> (I, J), padded to a multiple of 8
   int *tile_row0;    // index of tile (I, I)
   WorkItem *items;
+  int *atom_ptr, *atom_pix, *pix_ptr, *pix_atom;  // edgelet tables (else NULL)
   double2 *echo_tmp; // K clean-echo sums
   // split-BF16 operands of the Gram update, Npad x K words (NULL for FP32)
   unsigned *Ahi;
@@ -83,11 +99,12 @@ struct DevState {
 
 // ---- rows.hip ----
 hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
-                       int dict, int levels, hipStream_t st);
-hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
-                        int levels, hipStream_t st);
+                       const DictTabs &dt, hipStream_t st);
+// x = W c (npix entries).
+hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, const DictTabs &dt,
+                        hipStream_t st);
 // c = W^T x (adjoint of the image synthesis), padded to Npad.
-hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, int dict, int levels,
+hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, const DictTabs &dt,
                                 hipStream_t st);
 hipError_t launch_echo(const Geom &g, const double *pos, int s,
                        const float2 *rho, const float2 *noise, double snr_db,
@@ -95,6 +112,11 @@ hipError_t launch_echo(const Geom &g, const double *pos, int s,
                        hipStream_t st);
 hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
                          double *sig2, hipStream_t st);
+// Dense route to sigma^2 (any dictionary): G = A A^H (K x K, FP64 sums) from
+// the K x Npad rows A, then FP64 power iteration on nmat such matrices stored
+// back to back, one workgroup each, results to sig2[0 .. nmat).
+hipError_t launch_gram_kk(const Geom &g, const float2 *A, double2 *G, hipStream_t st);
+hipError_t launch_power_dense(int K, const double2 *G, int nmat, double *sig2, hipStream_t st);
 
 // ---- gram.hip ----
 // Correlation as its own launch (split-BF16 path): b += A^H (d e^{-i phi}).

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_echo_clean(Geom g, const double *__rest
   const double c4f = (4.0 * kPi / kC0) * (g.f0 + k * g.df);
   const double *p = pos + 3 * s;
   double2 acc = make_double2(0.0, 0.0);
-  for (int i = threadIdx.x; i < g.N; i += 256) {
+  for (int i = threadIdx.x; i < g.npix; i += 256) {
     const float2 r = rho[i];
     if (r.x == 0.f && r.y == 0.f) continue;
     const float2 e = phasor_neg(c4f * pixel_range(g, p, i));
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(Geom g, const double *__restri
   double2 acc[kToepDCh];
 #pragma unroll
   for (int j = 0; j < kToepDCh; ++j) acc[j] = make_double2(0.0, 0.0);
-  for (int i = threadIdx.x; i < g.N; i += 256) {
+  for (int i = threadIdx.x; i < g.npix; i += 256) {
     const double R = pixel_range(g, p, i);
 #pragma unroll
     for (int j = 0; j < kToepDCh; ++j) {
@@ -331,13 +331,179 @@ __global__ __launch_bounds__(256) void k_power_sigma2(int K, const double2 *__re
   if (threadIdx.x == 0) sig2[s] = q;
 }
 
+
+// ---------------------------------------------------------------------------
+// Edgelet dictionary (Section III-A): binary atoms, so A_s = F_s W is a
+// gather-sum of phasors and x = W c, c = W^T x are gather-sums too.
+
+// A_s[k, m] = sum over the pixels p of atom m of exp(-i 4 pi f_k R_p / c0):
+// thread per atom, kRowsKCh frequencies per thread; the FP64 range of each
+// pixel is formed once per thread and the phasors are added in pixel order.
+__global__ __launch_bounds__(256) void k_rows_edgelet(Geom g, const double *__restrict__ pos,
+                                                      int s, const int *__restrict__ atom_ptr,
+                                                      const int *__restrict__ atom_pix,
+                                                      float2 *__restrict__ A) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  const int k0 = blockIdx.y * kRowsKCh;
+  if (m >= g.Npad) return;
+  const int kn = min(kRowsKCh, g.K - k0);
+  float2 *out = A + static_cast<size_t>(k0) * g.Npad + m;
+  float2 acc[kRowsKCh];
+#pragma unroll
+  for (int kk = 0; kk < kRowsKCh; ++kk) acc[kk] = make_float2(0.f, 0.f);
+  if (m < g.N) {
+    const double c4 = 4.0 * kPi / kC0;
+    for (int q = atom_ptr[m]; q < atom_ptr[m + 1]; ++q) {
+      const double R = pixel_range(g, pos + 3 * s, atom_pix[q]);
+#pragma unroll
+      for (int kk = 0; kk < kRowsKCh; ++kk) {
+        if (kk < kn) {
+          const float2 e = phasor_neg((c4 * (g.f0 + (k0 + kk) * g.df)) * R);
+          acc[kk].x += e.x;
+          acc[kk].y += e.y;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < kRowsKCh; ++kk)
+    if (kk < kn) out[static_cast<size_t>(kk) * g.Npad] = acc[kk];
+}
+
+// x_p = sum of c_m over the atoms m containing pixel p (increasing m).
+__global__ __launch_bounds__(256) void k_image_edgelet(int npix, const int *__restrict__ pix_ptr,
+                                                       const int *__restrict__ pix_atom,
+                                                       const float2 *__restrict__ c,
+                                                       float2 *__restrict__ x) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int q = pix_ptr[p]; q < pix_ptr[p + 1]; ++q) {
+    const float2 v = c[pix_atom[q]];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  x[p] = acc;
+}
+
+// c_m = sum of x_p over the pixels p of atom m (increasing p); 0 past M.
+__global__ __launch_bounds__(256) void k_image_adjoint_edgelet(int M, int Npad,
+                                                               const int *__restrict__ atom_ptr,
+                                                               const int *__restrict__ atom_pix,
+                                                               const float2 *__restrict__ x,
+                                                               float2 *__restrict__ c) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= Npad) return;
+  float2 acc = make_float2(0.f, 0.f);
+  if (m < M) {
+    for (int q = atom_ptr[m]; q < atom_ptr[m + 1]; ++q) {
+      const float2 v = x[atom_pix[q]];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+  }
+  c[m] = acc;
+}
+
+constexpr int kKKB = 16;   // G block edge
+constexpr int kKKM = 64;   // coefficients staged per step
+
+// G = A A^H (K x K) with FP64 sums over the M coefficients in increasing
+// order: G[k, l] = sum_m A[k, m] conj(A[l, m]).  Workgroup = 16 x 16 block.
+__global__ __launch_bounds__(256) void k_gram_kk(int K, int Npad, int M,
+                                                 const float2 *__restrict__ A,
+                                                 double2 *__restrict__ G) {
+  __shared__ float2 ak[kKKB][kKKM + 1];
+  __shared__ float2 al[kKKB][kKKM + 1];
+  const int tx = threadIdx.x % kKKB, ty = threadIdx.x / kKKB;
+  const int k = blockIdx.x * kKKB + ty, l = blockIdx.y * kKKB + tx;
+  double re = 0.0, im = 0.0;
+  for (int m0 = 0; m0 < M; m0 += kKKM) {
+    for (int e = threadIdx.x; e < kKKB * kKKM; e += 256) {
+      const int r = e / kKKM, q = e % kKKM;
+      const int kr = blockIdx.x * kKKB + r, lr = blockIdx.y * kKKB + r, m = m0 + q;
+      ak[r][q] = (kr < K && m < M) ? A[static_cast<size_t>(kr) * Npad + m] : make_float2(0.f, 0.f);
+      al[r][q] = (lr < K && m < M) ? A[static_cast<size_t>(lr) * Npad + m] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int q = 0; q < kKKM; ++q) {
+      const float2 a = ak[ty][q], b = al[tx][q];
+      // a * conj(b)
+      re += static_cast<double>(a.x) * b.x + static_cast<double>(a.y) * b.y;
+      im += static_cast<double>(a.y) * b.x - static_cast<double>(a.x) * b.y;
+    }
+    __syncthreads();
+  }
+  if (k < K && l < K) G[static_cast<size_t>(k) * K + l] = make_double2(re, im);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// sigma^2 = lambda_max(G) for a dense Hermitian K x K matrix, FP64 power
+// iteration with the same start and stopping rule as k_power_sigma2.  One
+// workgroup per matrix; wave w forms y_k for rows k = w, w + 4, ... with the
+// lanes striding over l (coalesced rows) and a fixed-order wave sum.
+__global__ __launch_bounds__(256) void k_power_dense(int K, const double2 *__restrict__ Gall,
+                                                     double *__restrict__ sig2) {
+  extern __shared__ double2 sh[];
+  double2 *v = sh;       // K
+  double2 *y = sh + K;   // K
+  __shared__ double2 red[256];
+  __shared__ int done;
+  const double2 *G = Gall + static_cast<size_t>(blockIdx.x) * K * K;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(1.0 / sqrt(static_cast<double>(K)), 0.0);
+  if (threadIdx.x == 0) done = 0;
+  __syncthreads();
+  double q = 0.0, q_prev = 0.0;
+  for (int step = 0; step < kPowerMaxSteps; ++step) {
+    for (int k = wave; k < K; k += 4) {
+      double re = 0.0, im = 0.0;
+      for (int l = lane; l < K; l += 64) {
+        const double2 m = G[static_cast<size_t>(k) * K + l], x = v[l];
+        re += m.x * x.x - m.y * x.y;
+        im += m.x * x.y + m.y * x.x;
+      }
+      re = wave_sum_f64(re);
+      im = wave_sum_f64(im);
+      if (lane == 0) y[k] = make_double2(re, im);
+    }
+    __syncthreads();
+    double2 part = make_double2(0.0, 0.0);  // (Re v^H y, |y|^2)
+    for (int k = threadIdx.x; k < K; k += 256) {
+      part.x += v[k].x * y[k].x + v[k].y * y[k].y;
+      part.y += y[k].x * y[k].x + y[k].y * y[k].y;
+    }
+    const double2 tot = block_sum_d2(part, red);
+    q = tot.x;
+    if (threadIdx.x == 0) {
+      if ((step > 0 && fabs(q - q_prev) <= kPowerRelTol * fabs(q)) || tot.y == 0.0) done = 1;
+    }
+    __syncthreads();
+    if (done) break;
+    q_prev = q;
+    const double inv = 1.0 / sqrt(tot.y);
+    for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(y[k].x * inv, y[k].y * inv);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sig2[blockIdx.x] = q;
+}
+
 }  // namespace
 
 hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
-                       int dict, int levels, hipStream_t st) {
-  if (dict == 1) {
+                       const DictTabs &dt, hipStream_t st) {
+  if (dt.kind == 1) {
     const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
-    hipLaunchKernelGGL(k_rows_haar, dim3(g.K), dim3(kHaarThreads), lds, st, g, pos, s, levels, A);
+    hipLaunchKernelGGL(k_rows_haar, dim3(g.K), dim3(kHaarThreads), lds, st, g, pos, s, dt.levels, A);
+  } else if (dt.kind == 2) {
+    dim3 grid((g.Npad + 255) / 256, (g.K + kRowsKCh - 1) / kRowsKCh);
+    hipLaunchKernelGGL(k_rows_edgelet, grid, dim3(256), 0, st, g, pos, s, dt.atom_ptr, dt.atom_pix, A);
   } else {
     dim3 grid((g.Npad + 255) / 256, (g.K + kRowsKCh - 1) / kRowsKCh);
     hipLaunchKernelGGL(k_rows_identity, grid, dim3(256), 0, st, g, pos, s, A);
@@ -345,22 +511,28 @@ hipError_t launch_rows(const Geom &g, const double *pos, int s, float2 *A,
   return hipGetLastError();
 }
 
-hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, int dict,
-                        int levels, hipStream_t st) {
-  if (dict == 1) {
+hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, const DictTabs &dt,
+                        hipStream_t st) {
+  if (dt.kind == 1) {
     const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
-    hipLaunchKernelGGL(k_image_haar, dim3(1), dim3(kHaarThreads), lds, st, g, levels, c, x);
+    hipLaunchKernelGGL(k_image_haar, dim3(1), dim3(kHaarThreads), lds, st, g, dt.levels, c, x);
+  } else if (dt.kind == 2) {
+    hipLaunchKernelGGL(k_image_edgelet, dim3((g.npix + 255) / 256), dim3(256), 0, st, g.npix,
+                       dt.pix_ptr, dt.pix_atom, c, x);
   } else {
     hipLaunchKernelGGL(k_copy_c64, dim3((g.N + 255) / 256), dim3(256), 0, st, c, x, g.N);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, int dict, int levels,
+hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, const DictTabs &dt,
                                 hipStream_t st) {
-  if (dict == 1) {
+  if (dt.kind == 1) {
     const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
-    hipLaunchKernelGGL(k_analysis_haar, dim3(1), dim3(kHaarThreads), lds, st, g, levels, x, c);
+    hipLaunchKernelGGL(k_analysis_haar, dim3(1), dim3(kHaarThreads), lds, st, g, dt.levels, x, c);
+  } else if (dt.kind == 2) {
+    hipLaunchKernelGGL(k_image_adjoint_edgelet, dim3((g.Npad + 255) / 256), dim3(256), 0, st, g.N,
+                       g.Npad, dt.atom_ptr, dt.atom_pix, x, c);
   } else {
     hipLaunchKernelGGL(k_copy_pad_c64, dim3((g.Npad + 255) / 256), dim3(256), 0, st, x, c, g.N, g.Npad);
   }
@@ -383,6 +555,19 @@ hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
   hipLaunchKernelGGL(k_toeplitz, grid, dim3(256), 0, st, g, pos, gtoep);
   const size_t lds = 3 * static_cast<size_t>(g.K) * sizeof(double2);
   hipLaunchKernelGGL(k_power_sigma2, dim3(g.npos), dim3(256), lds, st, g.K, gtoep, sig2);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_kk(const Geom &g, const float2 *A, double2 *G, hipStream_t st) {
+  const int nbk = (g.K + kKKB - 1) / kKKB;
+  hipLaunchKernelGGL(k_gram_kk, dim3(nbk, nbk), dim3(256), 0, st, g.K, g.Npad, g.N, A, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_power_dense(int K, const double2 *G, int nmat, double *sig2, hipStream_t st) {
+  if (nmat <= 0) return hipSuccess;
+  const size_t lds = 2 * static_cast<size_t>(K) * sizeof(double2);
+  hipLaunchKernelGGL(k_power_dense, dim3(nmat), dim3(256), lds, st, K, G, sig2);
   return hipGetLastError();
 }
 

@@ -22,7 +22,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int N = 0, Npad = 0, nb = 0, K = 0, npos = 0, chunk = 4, nparts = 0;
+  // N: coefficient count M (length of b, c, ...); npix: pixels
+  int N = 0, Npad = 0, nb = 0, K = 0, npos = 0, chunk = 4, nparts = 0, npix = 0;
+  size_t nnz = 0;  // edgelet: total pixels over all atoms
+  size_t atom_ptr = 0, atom_pix = 0, pix_ptr = 0, pix_atom = 0;
   size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
@@ -49,6 +52,61 @@ size_t count_items(int nb, int chunk) {
   return n;
 }
 
+// Edgelet atoms of the dictionary (rule in include/ofista.h): pixel lists
+// in atom order.  Returns the atom count, or -1 when a length is out of range.
+// Floating-point contraction is off so that every rounding happens in the
+// order written (x0 + u*c, then + 0.5, then - 1e-9).
+long long edgelet_atoms(const ofista_config *c, std::vector<int> *ptr, std::vector<int> *pix) {
+#pragma clang fp contract(off)
+  const int n = c->n_x;
+  const double kDeg = 3.14159265358979323846 / 180.0;
+  long long M = 0;
+  std::vector<int> one;
+  if (ptr) ptr->assign(1, 0);
+  if (pix) pix->clear();
+  for (int r = 0; r < c->n_edge_rotations; ++r) {
+    const double psi = c->edge_rotations_deg[r] * kDeg;
+    const double cs = std::cos(psi), sn = std::sin(psi);
+    for (int li = 0; li < c->n_edge_lengths; ++li) {
+      const int len = c->edge_lengths[li];
+      if (len < 1 || len > n - 1) return -1;
+      for (int y0 = 0; y0 < n; ++y0)
+        for (int x0 = 0; x0 < n; ++x0) {
+          one.clear();
+          bool inside = true;
+          for (int t = 0; t < len && inside; ++t) {
+            const double u = t - (len - 1) / 2.0;
+            const double vx = x0 + u * cs;
+            const double vy = y0 + u * sn;
+            const long long ix = static_cast<long long>(std::floor(vx + 0.5 - 1e-9));
+            const long long iy = static_cast<long long>(std::floor(vy + 0.5 - 1e-9));
+            if (ix < 0 || ix >= n || iy < 0 || iy >= n) inside = false;
+            else one.push_back(static_cast<int>(iy * n + ix));
+          }
+          if (!inside) continue;
+          std::sort(one.begin(), one.end());
+          one.erase(std::unique(one.begin(), one.end()), one.end());
+          ++M;
+          if (pix) pix->insert(pix->end(), one.begin(), one.end());
+          if (ptr) ptr->push_back(static_cast<int>(pix ? pix->size() : 0));
+        }
+    }
+  }
+  return M;
+}
+
+// Coefficient count and total atom pixels for a checked config.
+long long coef_count(const ofista_config *c, size_t *nnz) {
+  if (c->dict != OFISTA_DICT_EDGELET) {
+    if (nnz) *nnz = 0;
+    return static_cast<long long>(c->n_x) * c->n_y;
+  }
+  std::vector<int> ptr, pix;
+  const long long M = edgelet_atoms(c, &ptr, &pix);
+  if (nnz) *nnz = pix.size();
+  return M;
+}
+
 // Run length of the FISTA work items.  Runs of 2 tiles measured faster than
 // runs of 4 or 8 at both N = 4096 and N = 16384 (more workgroups in flight).
 int pick_chunk(int) { return kChunk; }
@@ -70,7 +128,35 @@ ofista_status check(const ofista_config *c, std::string *why) {
   if (c->n_freq < 1 || c->n_freq > kMaxFreq) return bad("n_freq must be in [1, 1024]");
   if (!std::isfinite(c->freq0_hz) || !std::isfinite(c->dfreq_hz))
     return bad("frequencies must be finite");
-  if (c->dict != OFISTA_DICT_IDENTITY && c->dict != OFISTA_DICT_HAAR2D) return bad("unknown dict");
+  if (c->dict != OFISTA_DICT_IDENTITY && c->dict != OFISTA_DICT_HAAR2D &&
+      c->dict != OFISTA_DICT_EDGELET)
+    return bad("unknown dict");
+  if (c->dict == OFISTA_DICT_EDGELET) {
+    if (c->n_x != c->n_y) return bad("edgelet dictionary needs a square grid");
+    if (c->n_x < 2) return bad("edgelet dictionary needs n_x >= 2");
+    if (c->n_edge_lengths < 1 || !c->edge_lengths) return bad("edgelet lengths missing");
+    if (c->n_edge_rotations < 1 || !c->edge_rotations_deg) return bad("edgelet rotations missing");
+    if (static_cast<long long>(c->n_edge_lengths) * c->n_edge_rotations > 4096)
+      return bad("too many edgelet lengths x rotations");
+    for (int i = 0; i < c->n_edge_lengths; ++i)
+      if (c->edge_lengths[i] < 1 || c->edge_lengths[i] > c->n_x - 1)
+        return bad("edgelet lengths must be in [1, n_x - 1]");
+    for (int i = 0; i < c->n_edge_rotations; ++i)
+      if (!std::isfinite(c->edge_rotations_deg[i])) return bad("edgelet rotations must be finite");
+    const long long M = edgelet_atoms(c, nullptr, nullptr);
+    if (M < 1) return bad("the edgelet dictionary has no atom on this grid");
+    if (M > (1LL << 18)) {
+      if (why) *why = "edgelet dictionary limited to M <= 262144 atoms";
+      return OFISTA_E_UNSUPPORTED;
+    }
+    // the per-position K x K FP64 matrices of sigma^2 borrow the H region
+    const long long nbm = (M + kTile - 1) / kTile;
+    const long long hbytes = nbm * (nbm + 1) / 2 * kTile * kTile * 8;
+    if (static_cast<long long>(c->n_freq) * c->n_freq * 16 > hbytes) {
+      if (why) *why = "edgelet dictionary: K*K*16 bytes exceed the H storage";
+      return OFISTA_E_UNSUPPORTED;
+    }
+  }
   if (c->dict == OFISTA_DICT_HAAR2D) {
     if (c->haar_levels < 1) return bad("haar_levels must be >= 1");
     if (c->n_x != c->n_y) return bad("Haar dictionary needs a square grid");
@@ -102,7 +188,8 @@ ofista_status check(const ofista_config *c, std::string *why) {
 
 Layout layout(const ofista_config *c) {
   Layout L;
-  L.N = c->n_x * c->n_y;
+  L.npix = c->n_x * c->n_y;
+  L.N = static_cast<int>(coef_count(c, &L.nnz));
   L.nb = (L.N + kTile - 1) / kTile;
   L.Npad = L.nb * kTile;
   L.K = c->n_freq;
@@ -139,6 +226,12 @@ Layout layout(const ofista_config *c) {
   L.tile_row0 = take(L.nb * sizeof(int));
   L.items = take(L.nitems * sizeof(WorkItem));
   L.echo_tmp = take(L.K * sizeof(double2));
+  if (c->dict == OFISTA_DICT_EDGELET) {
+    L.atom_ptr = take((static_cast<size_t>(L.N) + 1) * sizeof(int));
+    L.atom_pix = take(L.nnz * sizeof(int));
+    L.pix_ptr = take((static_cast<size_t>(L.npix) + 1) * sizeof(int));
+    L.pix_atom = take(L.nnz * sizeof(int));
+  }
   L.Ahi = L.Alo = 0;
   if (c->precision == OFISTA_PREC_SPLIT_BF16) {
     L.Ahi = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
@@ -201,6 +294,7 @@ struct ofista_ctx {
   ofista_config cfg{};
   Layout L;
   Geom g{};
+  DictTabs dt{};
   DevState d{};
   hipStream_t st = nullptr;
   int device = 0;
@@ -315,6 +409,11 @@ int32_t ofista_tile(void) { return kTile; }
 
 ofista_status ofista_check_config(const ofista_config *cfg) { return check(cfg, nullptr); }
 
+int64_t ofista_coef_count(const ofista_config *cfg) {
+  if (check(cfg, nullptr) != OFISTA_OK) return -1;
+  return coef_count(cfg, nullptr);
+}
+
 size_t ofista_workspace_bytes(const ofista_config *cfg) {
   if (check(cfg, nullptr) != OFISTA_OK) return 0;
   return layout(cfg).total;
@@ -338,7 +437,9 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   ofista_ctx *c = new (std::nothrow) ofista_ctx();
   if (!c) return OFISTA_E_ARG;
   c->cfg = *cfg;
-  c->cfg.pos_xyz = nullptr;  // host table is not kept
+  c->cfg.pos_xyz = nullptr;  // host tables are not kept
+  c->cfg.edge_lengths = nullptr;
+  c->cfg.edge_rotations_deg = nullptr;
   c->L = L;
   c->st = static_cast<hipStream_t>(hip_stream);
   Geom &g = c->g;
@@ -348,6 +449,7 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   g.Npad = L.Npad;
   g.K = L.K;
   g.npos = L.npos;
+  g.npix = L.npix;
   g.x0 = cfg->x0;
   g.y0 = cfg->y0;
   g.dx = cfg->dx;
@@ -380,6 +482,12 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   d.echo_tmp = reinterpret_cast<double2 *>(base + L.echo_tmp);
   d.Ahi = L.Ahi ? reinterpret_cast<unsigned *>(base + L.Ahi) : nullptr;
   d.Alo = L.Alo ? reinterpret_cast<unsigned *>(base + L.Alo) : nullptr;
+  const bool edgelet = cfg->dict == OFISTA_DICT_EDGELET;
+  d.atom_ptr = edgelet ? reinterpret_cast<int *>(base + L.atom_ptr) : nullptr;
+  d.atom_pix = edgelet ? reinterpret_cast<int *>(base + L.atom_pix) : nullptr;
+  d.pix_ptr = edgelet ? reinterpret_cast<int *>(base + L.pix_ptr) : nullptr;
+  d.pix_atom = edgelet ? reinterpret_cast<int *>(base + L.pix_atom) : nullptr;
+  c->dt = DictTabs{cfg->dict, cfg->haar_levels, d.atom_ptr, d.atom_pix, d.pix_ptr, d.pix_atom};
 
   // host tables
   const int nb = L.nb;
@@ -423,7 +531,40 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
     return fail(e, "copy tile rows");
   if ((e = hipMemcpyAsync(d.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy work items");
-  if ((e = launch_sigma2(g, d.pos, d.gtoep, d.sig2, c->st)) != hipSuccess) return fail(e, "sigma2 kernels");
+  std::vector<int> aptr, apix, pptr, patom;
+  if (edgelet) {
+    edgelet_atoms(cfg, &aptr, &apix);
+    // pixel -> atoms, atoms in increasing order
+    pptr.assign(static_cast<size_t>(L.npix) + 1, 0);
+    for (int q : apix) ++pptr[static_cast<size_t>(q) + 1];
+    for (int p = 0; p < L.npix; ++p) pptr[p + 1] += pptr[p];
+    patom.assign(apix.size(), 0);
+    std::vector<int> fill(pptr.begin(), pptr.end() - 1);
+    for (int m = 0; m < L.N; ++m)
+      for (int q = aptr[m]; q < aptr[m + 1]; ++q) patom[fill[apix[q]]++] = m;
+    if ((e = hipMemcpyAsync(d.atom_ptr, aptr.data(), aptr.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.atom_pix, apix.data(), apix.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.pix_ptr, pptr.data(), pptr.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.pix_atom, patom.data(), patom.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+      return fail(e, "copy edgelet tables");
+    // sigma^2 per position from the K x K FP64 matrix A_s A_s^H, in batches
+    // that fit the (not yet used) H region
+    const size_t per = static_cast<size_t>(L.K) * L.K;
+    const size_t batch = std::max<size_t>(1, (L.ntiles * kTile * kTile * sizeof(float2)) / (per * sizeof(double2)));
+    double2 *Gs = reinterpret_cast<double2 *>(d.H);
+    for (int s0 = 0; s0 < L.npos; s0 += static_cast<int>(batch)) {
+      const int nm = static_cast<int>(std::min<size_t>(batch, static_cast<size_t>(L.npos - s0)));
+      for (int j = 0; j < nm; ++j) {
+        if ((e = launch_rows(g, d.pos, s0 + j, d.A, c->dt, c->st)) != hipSuccess ||
+            (e = launch_gram_kk(g, d.A, Gs + static_cast<size_t>(j) * per, c->st)) != hipSuccess)
+          return fail(e, "sigma2 rows");
+      }
+      if ((e = launch_power_dense(L.K, Gs, nm, d.sig2 + s0, c->st)) != hipSuccess)
+        return fail(e, "sigma2 power iteration");
+    }
+  } else if ((e = launch_sigma2(g, d.pos, d.gtoep, d.sig2, c->st)) != hipSuccess) {
+    return fail(e, "sigma2 kernels");
+  }
   st = do_reset(c);
   if (st != OFISTA_OK) {
     *out = c;
@@ -457,7 +598,7 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
   const int first = c->n == 0 ? 1 : 0;
   {
     ProfScope p(c, kProfRows);
-    OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
+    OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->dt, c->st));
   }
   if (seg_j >= 0) {
     OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
@@ -706,7 +847,7 @@ ofista_status ofista_backward(ofista_ctx *c, const void *d_grad_img, double *gra
   if (st != OFISTA_OK) return st;
   const std::vector<ofista_ctx::PulseRec> rec = c->rec;  // the re-runs below must not record
   OF_CK(c, launch_image_adjoint(c->g, static_cast<const float2 *>(d_grad_img),
-                                seg_ptr(c, L.chat_bar, 0, 0), c->cfg.dict, c->cfg.haar_levels, c->st));
+                                seg_ptr(c, L.chat_bar, 0, 0), c->dt, c->st));
   OF_CK(c, launch_fill(c->base + L.Bbar, static_cast<size_t>(L.Npad) * 2, 0u, c->st));
   const int R = L.rec_every;
   const int nseg = (P + R - 1) / R;
@@ -748,8 +889,8 @@ ofista_status ofista_image(ofista_ctx *c, void *d_img_out) {
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   if (!d_img_out) return OFISTA_E_ARG;
-  OF_CK(c, launch_image(c->g, c->d.cbuf[c->G & 1], static_cast<float2 *>(d_img_out), c->cfg.dict,
-                        c->cfg.haar_levels, c->st));
+  OF_CK(c, launch_image(c->g, c->d.cbuf[c->G & 1], static_cast<float2 *>(d_img_out), c->dt,
+                        c->st));
   return OFISTA_OK;
 }
 
@@ -768,7 +909,7 @@ ofista_status ofista_rows(ofista_ctx *c, int32_t s, void *d_out) {
   if (st != OFISTA_OK) return st;
   if (!d_out) return OFISTA_E_ARG;
   if (s < 0 || s >= c->L.npos) return OFISTA_E_RANGE;
-  OF_CK(c, launch_rows(c->g, c->d.pos, s, c->d.A, c->cfg.dict, c->cfg.haar_levels, c->st));
+  OF_CK(c, launch_rows(c->g, c->d.pos, s, c->d.A, c->dt, c->st));
   OF_CK(c, hipMemcpy2DAsync(d_out, static_cast<size_t>(c->L.N) * sizeof(float2), c->d.A,
                             static_cast<size_t>(c->L.Npad) * sizeof(float2),
                             static_cast<size_t>(c->L.N) * sizeof(float2), c->L.K,

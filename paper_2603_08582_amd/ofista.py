@@ -17,7 +17,7 @@ import torch
 _LIB_PATH = Path(__file__).resolve().with_name("libofista.so")
 _lib = None
 
-DICT = {"identity": 0, "haar": 1}
+DICT = {"identity": 0, "haar": 1, "edgelet": 2}
 PRECISION = {"fp32": 0, "split_bf16": 1}
 LIPSCHITZ = {"running": 0, "bound": 1}
 MOMENTUM = {"fista": 0, "restart": 1, "ista": 2}
@@ -46,6 +46,9 @@ class OfistaConfig(ctypes.Structure):
         ("precision", ctypes.c_int32), ("lipschitz", ctypes.c_int32),
         ("momentum", ctypes.c_int32), ("record_every", ctypes.c_int32),
         ("max_pulses", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+        ("n_edge_lengths", ctypes.c_int32), ("edge_lengths", ctypes.POINTER(ctypes.c_int32)),
+        ("n_edge_rotations", ctypes.c_int32),
+        ("edge_rotations_deg", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -71,6 +74,7 @@ def lib() -> ctypes.CDLL:
         "ofista_workspace_bytes": (sz, [cfgp]),
         "ofista_state_bytes": (sz, [cfgp]),
         "ofista_check_config": (i32, [cfgp]),
+        "ofista_coef_count": (ctypes.c_int64, [cfgp]),
         "ofista_create": (i32, [cfgp, vp, sz, vp, ctypes.POINTER(vp)]),
         "ofista_reset": (i32, [vp]),
         "ofista_push_pulse": (i32, [vp, vp, i32, f64]),
@@ -103,10 +107,12 @@ def lib() -> ctypes.CDLL:
 def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
                 dictionary="identity", haar_levels=0, lam=0.05, lam_relative=True,
                 precision="fp32", lipschitz="running", momentum="fista",
-                record_every=0, max_pulses=0, max_iters=0):
+                record_every=0, max_pulses=0, max_iters=0, edge_lengths=(), edge_rotations=()):
     """Build an OfistaConfig; returns (config, keepalive) -- keep the second
-    value alive while the config is in use (it owns the position table)."""
+    value alive while the config is in use (it owns the host tables)."""
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
+    lens = np.ascontiguousarray(np.asarray(edge_lengths, dtype=np.int32).reshape(-1))
+    rots = np.ascontiguousarray(np.asarray(edge_rotations, dtype=np.float64).reshape(-1))
     cfg = OfistaConfig(
         n_x=n_x, n_y=n_y, x0=x0, y0=y0, dx=dx, dy=dy, n_pos=pos.shape[0],
         pos_xyz=pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -114,8 +120,11 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
         dict=DICT[dictionary], haar_levels=haar_levels, lambda_=lam,
         lambda_relative=1 if lam_relative else 0, precision=PRECISION[precision],
         lipschitz=LIPSCHITZ[lipschitz], momentum=MOMENTUM[momentum],
-        record_every=record_every, max_pulses=max_pulses, max_iters=max_iters)
-    return cfg, pos
+        record_every=record_every, max_pulses=max_pulses, max_iters=max_iters,
+        n_edge_lengths=lens.size, edge_lengths=lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        n_edge_rotations=rots.size,
+        edge_rotations_deg=rots.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return cfg, (pos, lens, rots)
 
 
 def workspace_bytes(cfg: OfistaConfig) -> int:
@@ -124,6 +133,11 @@ def workspace_bytes(cfg: OfistaConfig) -> int:
 
 def check_config(cfg: OfistaConfig) -> int:
     return int(lib().ofista_check_config(ctypes.byref(cfg)))
+
+
+def coef_count(cfg: OfistaConfig) -> int:
+    """M, the number of coefficients (dictionary atoms); -1 if cfg is invalid."""
+    return int(lib().ofista_coef_count(ctypes.byref(cfg)))
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -140,8 +154,9 @@ class OnlineFista:
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.cfg, self._pos = make_config(**cfg_kwargs)
-        self.N = self.cfg.n_x * self.cfg.n_y
+        self.cfg, self._tables = make_config(**cfg_kwargs)
+        self.N = self.cfg.n_x * self.cfg.n_y   # pixels
+        self.M = coef_count(self.cfg)          # coefficients
         self.K = self.cfg.n_freq
         self.n_pos = self.cfg.n_pos
         nbytes = workspace_bytes(self.cfg)
@@ -190,7 +205,7 @@ class OnlineFista:
         self._check(self._lib.ofista_push_pulse(self._ctx, _ptr(d), int(s), float(phase_corr)))
 
     def reconstruct(self, iters: int, out: torch.Tensor | None = None, copy: bool = True):
-        o = self._out(out, self.N) if copy else None
+        o = self._out(out, self.M) if copy else None
         self._check(self._lib.ofista_reconstruct(self._ctx, int(iters),
                                                  _ptr(o) if o is not None else None))
         return o
@@ -218,17 +233,17 @@ class OnlineFista:
         return o
 
     def rows(self, s: int):
-        o = torch.empty((self.K, self.N), dtype=torch.complex64, device=self.device)
+        o = torch.empty((self.K, self.M), dtype=torch.complex64, device=self.device)
         self._check(self._lib.ofista_rows(self._ctx, int(s), _ptr(o)))
         return o
 
     def gram(self):
-        o = torch.empty((self.N, self.N), dtype=torch.complex64, device=self.device)
+        o = torch.empty((self.M, self.M), dtype=torch.complex64, device=self.device)
         self._check(self._lib.ofista_gram(self._ctx, _ptr(o)))
         return o
 
     def gram_entries(self, i, j):
-        """H_n[i[t], j[t]] for pixel index sequences i, j (any N)."""
+        """H_n[i[t], j[t]] for coefficient index sequences i, j (any M)."""
         ii = torch.as_tensor(np.asarray(i), dtype=torch.int32).to(self.device).contiguous()
         jj = torch.as_tensor(np.asarray(j), dtype=torch.int32).to(self.device).contiguous()
         if ii.shape != jj.shape or ii.dim() != 1:
@@ -238,7 +253,7 @@ class OnlineFista:
         return o
 
     def vector(self, which: str):
-        o = torch.empty(self.N, dtype=torch.complex64, device=self.device)
+        o = torch.empty(self.M, dtype=torch.complex64, device=self.device)
         idx = {"b": 0, "c": 1, "w": 2}[which]
         self._check(self._lib.ofista_vector(self._ctx, idx, _ptr(o)))
         return o

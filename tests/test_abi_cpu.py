@@ -108,3 +108,57 @@ def test_state_bytes_grows_with_problem():
     sb = L.ofista_state_bytes(ctypes.byref(b))
     assert 0 < sa < sb
     assert sb >= (64 * 64 // 64) * (64 * 64 // 64 + 1) // 2 * 64 * 64 * 8
+
+
+def edgelet_cfg(n=10, lengths=(4,), rotations=(0.0, 90.0), **kw):
+    from paper_2603_08582_amd import ofista
+    from workload import library_kwargs, make_workload, spec
+    wl = make_workload(spec("small", n_side=n, patch_m=float(n), n_freq=16, n_points=2))
+    args = library_kwargs(wl, dictionary="edgelet", edge_lengths=lengths, edge_rotations=rotations)
+    args.update(kw)
+    return ofista.make_config(**args)
+
+
+@pytest.mark.parametrize("n,l", [(10, 4), (16, 2), (12, 5)])
+def test_edgelet_coefficient_count_closed_form(n, l):
+    """Axis-aligned atoms of l consecutive pixels: n (n - l + 1) per rotation."""
+    from paper_2603_08582_amd import ofista
+    cfg, keep = edgelet_cfg(n, (l,), (0.0, 90.0))
+    assert ofista.coef_count(cfg) == 2 * n * (n - l + 1)
+    one, keep1 = edgelet_cfg(n, (1,), (0.0,))
+    assert ofista.coef_count(one) == n * n
+
+
+def test_edgelet_counts_match_the_oracle_on_oblique_atoms():
+    from oracle import dictionary
+    from paper_2603_08582_amd import ofista
+    lens, rots = (2, 3, 5), (0.0, 30.0, 45.0, 100.0, 135.0)
+    cfg, keep = edgelet_cfg(12, lens, rots)
+    assert ofista.coef_count(cfg) == len(dictionary.edgelet_atoms(12, lens, rots))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(edge_lengths=(0,)), dict(edge_lengths=(10,)), dict(edge_lengths=()),
+    dict(edge_rotations=()), dict(edge_rotations=(float("nan"),)),
+])
+def test_bad_edgelet_config_rejected(kw):
+    from paper_2603_08582_amd import ofista
+    cfg, keep = edgelet_cfg(10, **{"lengths": kw.get("edge_lengths", (4,)),
+                                   "rotations": kw.get("edge_rotations", (0.0, 90.0))})
+    assert ofista.check_config(cfg) == -1
+    assert ofista.coef_count(cfg) == -1
+    assert ofista.workspace_bytes(cfg) == 0
+
+
+def test_edgelet_needs_a_square_grid():
+    from paper_2603_08582_amd import ofista
+    cfg, keep = edgelet_cfg(10)
+    cfg.n_y = 8
+    assert ofista.check_config(cfg) == -1
+
+
+def test_edgelet_workspace_grows_with_the_atom_count():
+    from paper_2603_08582_amd import ofista
+    a, ka = edgelet_cfg(16, (4,), (0.0,))
+    b, kb = edgelet_cfg(16, (4,), (0.0, 90.0))
+    assert ofista.workspace_bytes(b) > ofista.workspace_bytes(a) > 0

@@ -1,0 +1,163 @@
+"""GPU parity of the edgelet dictionary (Section III-A) against the FP64 oracle.
+
+The library builds its atom tables on the host from the same definition the
+oracle implements separately; identical pixel sets show up as rows that agree
+to FP32 rounding (a single differing pixel would move a row entry by O(1)).
+Tolerances: rows <= 4e-6 absolute (sums of up to 6 unit phasors), sigma^2 and
+the sufficient statistics <= 1e-5 relative, coefficients and images <= 1e-4
+relative L2 (the FP32 contract).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dictionary, sar
+from oracle.online_fista import OnlineFistaOracle
+from workload import library_kwargs, make_workload, spec
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.complex64))).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def edge_spec(n=16, lengths=(4,), rotations=(0.0, 90.0), **kw):
+    base = dict(n_side=n, patch_m=float(n), n_pulses=8, n_freq=32, n_points=0, n_segments=4,
+                dictionary="edgelet", edge_lengths=lengths, edge_rotations_deg=rotations,
+                inner_steps=20)
+    base.update(kw)
+    return spec("small", **base)
+
+
+def gpu(wl, **kw):
+    from paper_2603_08582_amd import OnlineFista
+    return OnlineFista(**library_kwargs(wl, **kw))
+
+
+@pytest.mark.parametrize("lengths,rotations", [
+    ((4,), (0.0, 90.0)),                       # the paper's first dictionary
+    ((2, 4, 6), (0.0,)),                       # the paper's second dictionary
+    ((2, 3, 5), (30.0, 45.0, 100.0, 135.0)),   # oblique atoms, rounding rule
+])
+def test_rows_match_oracle(lengths, rotations):
+    wl = make_workload(edge_spec(16, lengths, rotations))
+    g = gpu(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    assert g.M == o.M == len(dictionary.edgelet_atoms(16, lengths, rotations))
+    for s in (0, 5):
+        A = host(g.rows(s))
+        ref = o.rows(s)
+        assert A.shape == ref.shape
+        assert np.max(np.abs(A - ref)) < 4e-6
+
+
+def test_sigma2_and_statistics_match_oracle():
+    wl = make_workload(edge_spec(16, (4,), (0.0, 90.0), n_pulses=4))
+    d = sar.echoes(wl).astype(np.complex64)
+    g = gpu(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    dd = dev(d)
+    for p in range(4):
+        g.push_pulse(dd[p], p)
+        o.push_pulse(d[p].astype(np.complex128), p)
+        st = g.state()
+        assert abs(st["sigma2"] - o.sigma2) <= 1e-5 * o.sigma2
+        g.reconstruct(5, copy=False)
+        o.reconstruct(5)
+    assert rel(host(g.vector("b")), o.b) < 1e-5
+    assert rel(host(g.gram()), o.H) < 1e-5
+
+
+@pytest.mark.parametrize("lengths,rotations,n", [
+    ((4,), (0.0, 90.0), 16),
+    ((2, 4, 6), (0.0,), 16),
+    ((2, 3), (0.0, 45.0, 90.0, 135.0), 20),   # M = 2928: a ragged tile of 48
+])
+def test_online_run_matches_oracle(lengths, rotations, n):
+    wl = make_workload(edge_spec(n, lengths, rotations, n_pulses=10))
+    d = sar.echoes(wl).astype(np.complex64)
+    g = gpu(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    dd = dev(d)
+    m = wl.spec.inner_steps
+    for p in range(wl.spec.n_pulses):
+        g.push_pulse(dd[p], p)
+        c = g.reconstruct(m)
+        o.push_pulse(d[p].astype(np.complex128), p)
+        o.reconstruct(m)
+    err_c = rel(host(c), o.c)
+    err_x = rel(host(g.image()), o.image())
+    print(f"edgelet {lengths} {rotations} n={n} M={o.M}: coef {err_c:.2e} image {err_x:.2e}")
+    assert err_c < 1e-4 and err_x < 1e-4
+
+
+def test_differentiation_form_with_edgelets():
+    """Reverse pass through the edgelet image synthesis (x = W c) against the
+    oracle's FP64 reverse pass."""
+    from oracle import adjoint
+    s = edge_spec(12, (4,), (0.0, 90.0), n_pulses=6, inner_steps=4, phase_error_rad=0.3)
+    wl = make_workload(s)
+    d = sar.echoes(wl).astype(np.complex64).astype(np.complex128)
+    phases = np.random.default_rng(5).uniform(-0.2, 0.2, s.n_pulses)
+    target = np.abs(wl.rho)
+    lam = 0.3
+    L0, gl0, gp0 = adjoint.gradients(wl, d, lam, phases, s.inner_steps, target)
+    g = gpu(wl, record_every=3, max_pulses=s.n_pulses, max_iters=s.inner_steps)
+    g.set_lambda(lam)
+    dd = dev(d)
+    for n in range(s.n_pulses):
+        g.push_pulse(dd[n], n, float(phases[n]))
+        g.reconstruct(s.inner_steps, copy=False)
+    x = host(g.image())
+    mag = np.abs(x)
+    gx = np.where(mag > 0, 2 * (mag - target) * x / np.where(mag > 0, mag, 1), 0)
+    gl, gp = g.backward(dev(gx))
+    assert abs(gl - gl0) <= 1e-3 * abs(gl0)
+    assert np.linalg.norm(gp - gp0) <= 1e-3 * np.linalg.norm(gp0)
+
+
+def test_full_size_edgelet64_sampled():
+    """edgelet64 (64x64 pixels, M = 7808 atoms, K = 256, 128 pulses, m = 20)
+    run in full on the GPU; sampled H and b entries against the oracle formed
+    entry by entry from the rows of the sampled atoms, and a finite image."""
+    wl = make_workload("edgelet64")
+    s = wl.spec
+    d = sar.echoes(wl).astype(np.complex64)
+    g = gpu(wl)
+    assert g.M == 2 * 64 * 61
+    dd = dev(d)
+    for p in range(s.n_pulses):
+        g.push_pulse(dd[p], p)
+        g.reconstruct(s.inner_steps, copy=False)
+    x = host(g.image())
+    assert np.all(np.isfinite(x))
+    rng = np.random.default_rng(3)
+    i = rng.integers(0, g.M, 48)
+    j = rng.integers(0, g.M, 48)
+    i[:4] = j[:4] = [0, 61, 3904, 7807]           # diagonal entries at tile edges
+    Hs = host(g.gram_entries(i, j))
+    o = OnlineFistaOracle.from_workload(wl)
+    W = o.W
+    cols = np.unique(np.r_[i, j])
+    ref_H = np.zeros(len(i), complex)
+    ref_b = np.zeros(len(cols), complex)
+    where = {c: k for k, c in enumerate(cols)}
+    for p in range(s.n_pulses):
+        F = sar.forward_rows(wl.positions[p], wl.pixel_xyz(), wl.freqs())
+        A = F @ W[:, cols]
+        ref_H += np.sum(A[:, [where[a] for a in i]].conj() * A[:, [where[b] for b in j]], axis=0)
+        ref_b += A.conj().T @ d[p].astype(np.complex128)
+    assert np.max(np.abs(Hs - ref_H)) <= 1e-5 * np.max(np.abs(ref_H))
+    b = host(g.vector("b"))[cols]
+    assert rel(b, ref_b) < 1e-5
