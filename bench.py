@@ -150,8 +150,9 @@ def main():
 
     gram_avg = gram_ms / max(gram_n, 1)
     step_avg = step_ms / max(step_n, 1)
-    gram_flops = 4.0 * K * N * (N + 1)          # Hermitian upper triangle, per pulse
-    step_bytes = 4.0 * N * (N + 1)              # upper-triangle complex64 H, per FISTA step
+    M = g.M                                     # coefficients (= N except for edgelets)
+    gram_flops = 4.0 * K * M * (M + 1)          # Hermitian upper triangle, per pulse
+    step_bytes = 4.0 * M * (M + 1)              # upper-triangle complex64 H, per FISTA step
     if s.precision == "split_bf16":
         # three BF16 products per FP32 product (hi*hi + hi*lo + lo*hi)
         rl_gram = {"bound": "mfma", "achieved": 3 * gram_flops / (gram_avg * 1e-3) / 1e12,
@@ -170,6 +171,13 @@ def main():
         r["frac"] = r["achieved"] / r["peak"]
     dominant, other = (rl_step, rl_gram) if step_ms >= gram_ms else (rl_gram, rl_step)
 
+    if s.dictionary == "edgelet":
+        dict_desc = (f"edgelet(lengths {'/'.join(map(str, s.edge_lengths))}, rotations "
+                     f"{'/'.join(f'{r:g}' for r in s.edge_rotations_deg)} deg)")
+    elif s.dictionary == "haar":
+        dict_desc = f"haar({s.haar_levels})"
+    else:
+        dict_desc = "identity"
     out = {
         "metric": METRIC,
         "value": P / (ms * 1e-3),
@@ -184,9 +192,9 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"{s.name}: {s.n_side}x{s.n_side} pixels (N={N}), "
-                               f"{s.dictionary}({s.haar_levels}) dictionary, K={K}, "
+                               f"{dict_desc} dictionary (M={M}), K={K}, "
                                f"P={P} pulses, m={m} FISTA steps per pulse, one step = one image",
-                   "N": N, "K": K, "pulses": P, "inner_steps": m, "seed": s.seed,
+                   "N": N, "M": M, "K": K, "pulses": P, "inner_steps": m, "seed": s.seed,
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
                    "parallelism": "single GPU"},
         "fista_iters_per_s": P * m / (ms * 1e-3),
