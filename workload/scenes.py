@@ -11,6 +11,9 @@ m inner steps per pulse) at the sizes of the five benchmark configurations:
   ``xlarge``    256x256 pixels, 512 pulses over 40 deg,  K=1024, identity, split-BF16
   ``edgelet64``  64x64 pixels,  128 pulses over 20 deg,  K=256,  edgelets (length 4,
                  0 and 90 deg), scene of axis-aligned segments
+  ``session32``  32x32 pixels, 1000 candidate positions over 2 deg at 4 km (the
+                 collection of Section IV-A), Bernoulli pulse selection, K=64,
+                 edgelets (length 4, 0 and 90 deg), one square target
 
 Readings of details the paper leaves open (all listed in the design doc):
 
@@ -27,6 +30,11 @@ Readings of details the paper leaves open (all listed in the design doc):
 * a segment target is an axis-aligned run of pixels (horizontal or vertical
   with probability 1/2, length drawn from ``segment_px``, start uniform among
   the positions that keep it on the grid) carrying one complex reflectivity;
+* a square target is the outline of a ``square_px``-pixel square (its four
+  sides, each a run of ``square_px`` pixels, added up, so corners count twice)
+  with one complex reflectivity, placed uniformly on the grid;
+* every position also gets one uniform draw u_s in [0, 1) for the Bernoulli
+  selection of Section IV-A (position s transmits when u_s < bernoulli_p);
 * noise draws are unit-variance circular complex normals (Re, Im ~ N(0, 1/2));
   the consumer scales them to the stated SNR per pulse.
 
@@ -63,6 +71,11 @@ class WorkloadSpec:
     edge_rotations_deg: tuple = ()  # edgelet rotations, degrees
     n_segments: int = 0             # axis-aligned segment targets
     segment_px: tuple = (4, 8)      # their lengths, pixels
+    n_squares: int = 0              # square-outline targets
+    square_px: int = 4              # their side, pixels
+    bernoulli_p: float = 1.0        # probability that a position transmits
+    ideal_count: int = 0            # stop once this many |c| > large_thresh (0: never)
+    large_thresh: float = 2e-2      # "large coefficient" threshold of Section IV-B
     snr_db: float = 30.0
     inner_steps: int = 20       # m of Algorithm 1
     phase_error_rad: float = 0.0  # per-pulse phase errors U[-e, e] (0 = none)
@@ -106,6 +119,12 @@ CONFIGS = {
         n_freq=256, f_lo=9.8e9, f_hi=10.2e9, n_points=0, n_segments=8,
         dictionary="edgelet", edge_lengths=(4,), edge_rotations_deg=(0.0, 90.0),
         snr_db=30.0, inner_steps=20, seed=2608),
+    "session32": WorkloadSpec(
+        name="session32", n_side=32, patch_m=30.0, n_pulses=1000, azimuth_deg=2.0,
+        n_freq=64, f_lo=9.9e9, f_hi=10.1e9, n_points=0, n_squares=1,
+        dictionary="edgelet", edge_lengths=(4,), edge_rotations_deg=(0.0, 90.0),
+        snr_db=30.0, inner_steps=20, radius_m=4_000.0, bernoulli_p=0.1, ideal_count=4,
+        seed=2609),
 }
 
 
@@ -130,6 +149,7 @@ class Workload:
     noise: np.ndarray           # (P, K) complex128, unit-variance draws
     phase_err: np.ndarray       # (P,) float64 true per-pulse phase errors
     support: np.ndarray = field(default=None)  # sorted nonzero pixel indices
+    select_u: np.ndarray = field(default=None)  # (P,) uniforms of the Bernoulli selection
 
     @property
     def n_pixels(self) -> int:
@@ -159,7 +179,7 @@ def _draw_magnitudes(rng, kind: str, size: int) -> np.ndarray:
 def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
     """Draw one workload.  All draws come from one PCG64 stream in a fixed order:
     point pixels, point magnitudes, point phases, line parameters, segment
-    parameters, noise, phase errors."""
+    parameters, square parameters, noise, phase errors, selection draws."""
     if isinstance(s, str):
         s = CONFIGS[s]
     rng = np.random.Generator(np.random.PCG64(s.seed if seed is None else seed))
@@ -209,6 +229,21 @@ def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
             idx = b * n + run if horiz[j] else run * n + b
             rho[idx] += smag[j] * np.exp(1j * sph[j])
 
+    if s.n_squares:
+        side = s.square_px
+        qa = rng.random(s.n_squares)
+        qb = rng.random(s.n_squares)
+        qmag = _draw_magnitudes(rng, s.magnitude, s.n_squares)
+        qph = rng.uniform(0.0, 2 * math.pi, s.n_squares)
+        for j in range(s.n_squares):
+            x = int(qa[j] * (n - side + 1))
+            y = int(qb[j] * (n - side + 1))
+            run = np.arange(side)
+            amp = qmag[j] * np.exp(1j * qph[j])
+            for idx in (y * n + x + run, (y + side - 1) * n + x + run,
+                        (y + run) * n + x, (y + run) * n + x + side - 1):
+                rho[idx] += amp
+
     g = rng.standard_normal((P, K, 2))
     noise = (g[..., 0] + 1j * g[..., 1]) / math.sqrt(2.0)
 
@@ -216,6 +251,7 @@ def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
         phase_err = rng.uniform(-s.phase_error_rad, s.phase_error_rad, P)
     else:
         phase_err = np.zeros(P)
+    select_u = rng.random(P)
 
     theta = np.deg2rad(s.azimuth_deg) * np.arange(P) / max(P - 1, 1)
     positions = np.stack([s.radius_m * np.cos(theta), s.radius_m * np.sin(theta),
@@ -224,7 +260,7 @@ def make_workload(s: WorkloadSpec | str, seed: int | None = None) -> Workload:
     dfreq = (s.f_hi - s.f_lo) / (K - 1) if K > 1 else 0.0
     return Workload(spec=s, x0=x0, y0=x0, dx=dx, dy=dx, positions=positions,
                     freq0=s.f_lo, dfreq=dfreq, rho=rho, noise=noise,
-                    phase_err=phase_err, support=np.flatnonzero(rho))
+                    phase_err=phase_err, support=np.flatnonzero(rho), select_u=select_u)
 
 
 def library_kwargs(wl: Workload, **overrides) -> dict:
