@@ -92,3 +92,34 @@ def test_session32_settles_on_the_square():
     snr_ofista = session.snr_db(o.image(), wl.support)
     snr_bp = session.snr_db(session.backprojection(wl, d, pushed), wl.support)
     assert snr_ofista > snr_bp + 20
+
+
+# ---------------------------------------------------------------- store-all comparator
+def test_store_all_trajectory_equals_online():
+    """Section III-D comparator: sum_k G_k^H (G_k z - d_k) = H_n z - b_n, so the
+    stored-pulse method follows the Online FISTA trajectory (same lambda, L
+    rule and momentum) up to rounding."""
+    from oracle.store_all import StoreAllFistaOracle
+    wl = make_workload(spec("haar64", n_side=16, patch_m=16.0, n_pulses=6, n_freq=24,
+                            n_points=4, n_lines=1, haar_levels=2))
+    d = sar.echoes(wl)
+    a = OnlineFistaOracle.from_workload(wl)
+    b = StoreAllFistaOracle.from_workload(wl)
+    for s in range(6):
+        a.push_pulse(d[s], s, 0.1 * s)
+        b.push_pulse(d[s], s, 0.1 * s)
+        assert math.isclose(a.L, b.L, rel_tol=1e-10) and math.isclose(a.lam, b.lam, rel_tol=1e-12)
+        a.reconstruct(15)
+        b.reconstruct(15)
+        assert np.linalg.norm(a.c - b.c) <= 1e-10 * np.linalg.norm(a.c)
+
+
+def test_store_all_counts_table1():
+    from oracle import memory
+    from oracle.store_all import StoreAllFistaOracle
+    wl = make_workload(spec("small", n_side=8, patch_m=8.0, n_pulses=5, n_freq=16, n_points=2))
+    d = sar.echoes(wl)
+    b = StoreAllFistaOracle.from_workload(wl)
+    for s in range(5):
+        b.push_pulse(d[s], s)
+        assert b.stored_values() == memory.fista_values(64, 64, 16, s + 1)
