@@ -49,8 +49,9 @@ def traffic_for(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, pulses: int):
-    """The FP64 oracle as it stands, on the first `pulses` pulses."""
+def cpu_baseline(wl, pulses: int, positions=None):
+    """The FP64 oracle as it stands, on the first `pulses` pulses (of
+    `positions` when given: the Bernoulli-selected ones of a session)."""
     from oracle import sar
     from oracle.online_fista import OnlineFistaOracle
     try:
@@ -59,16 +60,19 @@ def cpu_baseline(wl, pulses: int):
                        if i.get("user_api") == "blas"), default=1)
     except Exception:
         threads = os.cpu_count() or 1
-    d = sar.echoes(wl)
+    order_all = list(range(wl.spec.n_pulses)) if positions is None else [int(p) for p in positions]
+    order = order_all[:pulses]
+    d = sar.echoes(wl, pulses=order)
     o = OnlineFistaOracle.from_workload(wl)
     m = wl.spec.inner_steps
     t0 = time.perf_counter()
-    for p in range(pulses):
+    for p in order:
         o.push_pulse(d[p], p)
         o.reconstruct(m)
     dt = time.perf_counter() - t0
+    pulses = len(order)
     return {"value": pulses / dt, "unit": "pulses/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {pulses} of {wl.spec.n_pulses} pulses of the same workload "
+            "sample": f"first {pulses} of the {len(order_all)} pulses of the same workload "
                       f"(push + {m} FISTA steps each), numpy complex128, {dt:.1f} s"}
 
 
@@ -101,12 +105,21 @@ def main():
     g = OnlineFista(device=dev, **library_kwargs(wl))
     stream = g.stream
 
+    # a collection session (Section IV-A): Bernoulli-selected positions and an
+    # early stop at the ideal large-coefficient count; otherwise every position
+    session_mode = s.bernoulli_p < 1.0 or s.ideal_count > 0
+    if session_mode:
+        from paper_2603_08582_amd import session as sess
+        sched = sess.bernoulli_schedule(wl.select_u, s.bernoulli_p)
+    else:
+        sched = np.arange(P)
+
     # inputs: echoes synthesised on the device from the seeded scene and noise
     rho = torch.from_numpy(wl.rho.astype(np.complex64)).to(dev)
     noise = torch.from_numpy(wl.noise.astype(np.complex64)).to(dev)
-    d = torch.empty((P, K), dtype=torch.complex64, device=dev)
-    for p in range(P):
-        g.echo(p, rho, noise[p], s.snr_db, float(wl.phase_err[p]), out=d[p])
+    d = torch.zeros((P, K), dtype=torch.complex64, device=dev)
+    for p in sched:
+        g.echo(int(p), rho, noise[p], s.snr_db, float(wl.phase_err[p]), out=d[p])
     torch.cuda.synchronize()
 
     if args.copy_calibration_mib:
@@ -118,8 +131,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    pulses_per_step = [P]
+
     def step():
         g.reset()
+        if session_mode:
+            res = sess.run_session(g, d, sched, m, ideal=s.ideal_count, threshold=s.large_thresh)
+            pulses_per_step[0] = len(res["pushed"])
+            return
         for p in range(P):
             g.push_pulse(d[p], p)
             g.reconstruct(m, copy=False)
@@ -180,7 +199,7 @@ def main():
         dict_desc = "identity"
     out = {
         "metric": METRIC,
-        "value": P / (ms * 1e-3),
+        "value": pulses_per_step[0] / (ms * 1e-3),
         "unit": "pulses/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -193,11 +212,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{s.name}: {s.n_side}x{s.n_side} pixels (N={N}), "
                                f"{dict_desc} dictionary (M={M}), K={K}, "
-                               f"P={P} pulses, m={m} FISTA steps per pulse, one step = one image",
-                   "N": N, "M": M, "K": K, "pulses": P, "inner_steps": m, "seed": s.seed,
+                               + (f"session over {P} positions: Bernoulli p={s.bernoulli_p:g} "
+                                  f"selects {len(sched)}, stop at {s.ideal_count} large "
+                                  f"coefficients after {pulses_per_step[0]} pulses"
+                                  if session_mode else f"P={P} pulses")
+                               + f", m={m} FISTA steps per pulse, one step = one image",
+                   "N": N, "M": M, "K": K, "pulses": pulses_per_step[0], "positions": P,
+                   "inner_steps": m, "seed": s.seed,
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
                    "parallelism": "single GPU"},
-        "fista_iters_per_s": P * m / (ms * 1e-3),
+        "fista_iters_per_s": pulses_per_step[0] * m / (ms * 1e-3),
         "roofline": {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": dominant["kernel"],
         "roofline_other": other,
@@ -205,7 +229,7 @@ def main():
         "image_finite": finite,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses, sched if session_mode else None)
     print(json.dumps(out), flush=True)
 
 

@@ -78,6 +78,16 @@ enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
    sigma_n^2 = ||A_s||_2^2 from an FP64 power iteration (at most 200 steps,
    stop at 1e-13 relative change of the Rayleigh quotient, start 1/sqrt(K)). */
 enum { OFISTA_LIP_RUNNING = 0, OFISTA_LIP_BOUND = 1 };
+/* What the state keeps (Section III-D, Table I).  GRAM: the running sufficient
+   statistics H_n, b_n (Online FISTA).  PULSES: the comparator that keeps every
+   received pulse (G_k = F_k W and d_k e^{-i phase_corr}, up to max_pulses of
+   them) and forms the gradient matrix-free, sum_k G_k^H (G_k z - d_k), with the
+   same lambda, L rule and momentum -- the same iterates in exact arithmetic,
+   different memory and work.  PULSES needs max_pulses >= 1, record_every = 0
+   and FP32; ofista_gram, ofista_gram_entries, the state record and
+   ofista_backward return OFISTA_E_UNSUPPORTED with it, and a push beyond
+   max_pulses returns OFISTA_E_STATE. */
+enum { OFISTA_STORE_GRAM = 0, OFISTA_STORE_PULSES = 1 };
 /* Momentum across pulses: FISTA = t carried from pulse to pulse (Algorithm 1);
    RESTART = t = 1 at every reconstruct; ISTA = no momentum (beta = 0). */
 enum { OFISTA_MOMENTUM_FISTA = 0, OFISTA_MOMENTUM_RESTART = 1, OFISTA_MOMENTUM_ISTA = 2 };
@@ -104,13 +114,17 @@ typedef struct ofista_config {
   int32_t record_every;    /* > 0: keep what ofista_backward needs, with a
                               state checkpoint every record_every pulses
                               (see ofista_backward)                          */
-  int32_t max_pulses;      /* pulses that can be recorded (record_every > 0) */
+  int32_t max_pulses;      /* pulses that can be recorded (record_every > 0)
+                              or stored (storage = PULSES)                    */
   int32_t max_iters;       /* inner steps per reconstruct that can be
                               recorded (record_every > 0)                    */
   int32_t n_edge_lengths;  /* EDGELET: number of lengths (>= 1)               */
   const int32_t *edge_lengths;      /* host, copied during ofista_create      */
   int32_t n_edge_rotations;         /* EDGELET: number of rotations (>= 1)    */
   const double *edge_rotations_deg; /* host, degrees, copied                  */
+  int32_t backprojection;  /* != 0: push_pulse also accumulates the BP image
+                              (see ofista_bp_image)                          */
+  int32_t storage;         /* OFISTA_STORE_*                                   */
 } ofista_config;
 
 typedef struct ofista_stats {
@@ -173,6 +187,20 @@ ofista_status ofista_reconstruct(struct ofista_ctx *ctx, int32_t iters,
    d_img_out: device, N complex64. */
 ofista_status ofista_image(struct ofista_ctx *ctx, void *d_img_out);
 
+/* BP baseline of Section IV-A: d_img_out (device, N complex64) receives
+   (1/n) sum over the n pushed pulses of F_s^H (d_s e^{-i phase_corr}), the
+   adjoint-imaged pulses averaged in the pixel domain (display it as
+   20 log10 |.|).  Needs backprojection != 0 in the config (else
+   OFISTA_E_STATE), and n >= 1 (else OFISTA_E_STATE).  The accumulator is
+   part of the state record. */
+ofista_status ofista_bp_image(struct ofista_ctx *ctx, void *d_img_out);
+
+/* Large-coefficient count of Section IV-B: the number of entries of c_hat
+   with |c| > threshold, |c| formed in FP32 (sqrtf of the FP32 sum of
+   squares) and compared with (float)threshold.  Synchronises the stream
+   (the count is returned on the host). */
+ofista_status ofista_count_large(struct ofista_ctx *ctx, double threshold, int64_t *count);
+
 /* Host copy of the scalar state.  Synchronises the stream. */
 ofista_status ofista_state(struct ofista_ctx *ctx, ofista_stats *out);
 
@@ -200,12 +228,13 @@ ofista_status ofista_gram_entries(struct ofista_ctx *ctx, int32_t n, const int32
 ofista_status ofista_gram(struct ofista_ctx *ctx, void *d_out);
 ofista_status ofista_vector(struct ofista_ctx *ctx, int32_t which, void *d_out);
 
-/* Resumable state record (n, t, L, lambda, power vector, c_hat, b, H), so that
+/* Resumable state record (n, t, L, lambda, power vector, c_hat, b, H, and the
+   BP accumulator when enabled), so that
    a run split at any pulse and resumed equals the uninterrupted run.  The
    buffer is caller-owned device memory of ofista_state_bytes(cfg) bytes;
    alignment padding inside it is left unwritten.  Export synchronises the
    stream; import synchronises it and forgets any recorded history. */
-size_t ofista_state_bytes(const ofista_config *cfg);
+size_t ofista_state_bytes(const ofista_config *cfg);  /* 0 for PULSES storage */
 ofista_status ofista_export_state(struct ofista_ctx *ctx, void *d_buf);
 ofista_status ofista_import_state(struct ofista_ctx *ctx, const void *d_buf);
 
@@ -240,7 +269,8 @@ ofista_status ofista_set_lambda(struct ofista_ctx *ctx, double lambda);
    b += A_s^H d fused in), 1 FISTA-step tile pass (the H z / H w streaming),
    2 rows, 3 correlation (separate launch on the split-BF16 path only),
    4 scalars, 5 FISTA-step update (slot sums, shrink, momentum, power
-   vector). */
+   vector), 6 and 7 the two passes over the stored pulses of the PULSES
+   storage (G z - d, G w; then G^H of both). */
 ofista_status ofista_profile(struct ofista_ctx *ctx, int32_t enable);
 ofista_status ofista_kernel_time(struct ofista_ctx *ctx, int32_t kernel,
                                  double *total_ms, int64_t *launches);

@@ -6,6 +6,6 @@ include/ofista.h); this package holds its sources (csrc/), the build step
 """
 
 from .ofista import (  # noqa: F401
-    DICT, KERNEL, LIPSCHITZ, MOMENTUM, PRECISION, OfistaConfig, OfistaError,
+    DICT, KERNEL, LIPSCHITZ, MOMENTUM, PRECISION, STORAGE, OfistaConfig, OfistaError,
     OnlineFista, OnlineFistaFn, check_config, coef_count, lib, make_config, workspace_bytes,
 )

@@ -85,6 +85,7 @@ __device__ __forceinline__ int valid_slot(int v, int R, int chunk) {
   return v < R ? v : R + (v - R) * chunk;
 }
 
+template <bool PARTIALS>
 __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   __shared__ float4 red[kUpdParts][kUpdRows];
   __shared__ double wred[4];
@@ -93,7 +94,9 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   const int t = threadIdx.x;
   const int r = t % kUpdRows, part = t / kUpdRows;
   const int i = R * kTile + sub * kUpdRows + r;
-  const int nvalid = R + (nb - R + chunk - 1) / chunk;
+  // tile-pass slots: column partials j < R, then the run starts; store-all:
+  // the nchunks partial rows of P
+  const int nvalid = PARTIALS ? a.nchunks : R + (nb - R + chunk - 1) / chunk;
   // this row's inputs, loaded before the slots so both arrive together
   const bool live = t < kUpdRows && i < a.N;
   float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
@@ -107,14 +110,18 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   double m = 0.0;
   for (int j = t; j < nparts; j += 256) m += a.slot_prev[nparts + j];
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  const f32x4 *q = reinterpret_cast<const f32x4 *>(a.Q + static_cast<size_t>(R) * nb * kTile + (i - R * kTile));
+  const f32x4 *q = PARTIALS
+                       ? reinterpret_cast<const f32x4 *>(a.P + i)
+                       : reinterpret_cast<const f32x4 *>(a.Q + static_cast<size_t>(R) * nb * kTile + (i - R * kTile));
   for (int v0 = part; v0 < nvalid; v0 += kUpdParts * kUpdBatch) {
     f32x4 x[kUpdBatch];
 #pragma unroll
     for (int u = 0; u < kUpdBatch; ++u) {
       const int v = v0 + kUpdParts * u;
-      const int j = valid_slot(v < nvalid ? v : nvalid - 1, R, chunk);
-      x[u] = __builtin_nontemporal_load(q + static_cast<size_t>(j) * kTile);
+      const int vc = v < nvalid ? v : nvalid - 1;
+      const size_t off = PARTIALS ? static_cast<size_t>(vc) * a.Npad
+                                  : static_cast<size_t>(valid_slot(vc, R, chunk)) * kTile;
+      x[u] = __builtin_nontemporal_load(q + off);
     }
 #pragma unroll
     for (int u = 0; u < kUpdBatch; ++u) {
@@ -336,7 +343,124 @@ __global__ void k_init_power(float2 *w, double *slot0, double *slot1, int N, int
   }
 }
 
+// Large-coefficient count: integer atomics, so the result is exact whatever
+// the order.
+__global__ __launch_bounds__(256) void k_count_large(const float2 *__restrict__ c, int M, float thr,
+                                                     unsigned *__restrict__ count) {
+  unsigned n = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < M; i += gridDim.x * 256) {
+    const float2 v = c[i];
+    n += sqrtf(v.x * v.x + v.y * v.y) > thr ? 1u : 0u;
+  }
+  __shared__ unsigned red[256];
+  red[threadIdx.x] = n;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0]) atomicAdd(count, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Store-all comparator (Section III-D): gradient from the stored pulses,
+// two passes over the stacked operator per step.
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// One wave per stacked row r: U[r] = (G_r z - D_r, G_r w), lanes striding
+// over the coefficients (coalesced rows), fixed-order wave sums.
+__global__ __launch_bounds__(256) void k_store_forward(const float2 *__restrict__ G,
+                                                       const float2 *__restrict__ D, int rows,
+                                                       int Npad, int M,
+                                                       const float2 *__restrict__ z,
+                                                       const float2 *__restrict__ w,
+                                                       float4 *__restrict__ U) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;  // whole waves
+  const float2 *g = G + static_cast<size_t>(r) * Npad;
+  float zr = 0.f, zi = 0.f, wr = 0.f, wi = 0.f;
+  for (int m = lane; m < M; m += 64) {
+    const float2 a = g[m], x = z[m], y = w[m];
+    zr = fmaf(a.x, x.x, fmaf(-a.y, x.y, zr));
+    zi = fmaf(a.x, x.y, fmaf(a.y, x.x, zi));
+    wr = fmaf(a.x, y.x, fmaf(-a.y, y.y, wr));
+    wi = fmaf(a.x, y.y, fmaf(a.y, y.x, wi));
+  }
+  zr = wave_sum_f32(zr);
+  zi = wave_sum_f32(zi);
+  wr = wave_sum_f32(wr);
+  wi = wave_sum_f32(wi);
+  if (lane == 0) {
+    const float2 d = D[r];
+    U[r] = make_float4(zr - d.x, zi - d.y, wr, wi);
+  }
+}
+
+// P[c][m] = sum over the rows of chunk c of conj(G[r, m]) (U_z[r], U_w[r]),
+// rows in increasing order; thread per coefficient (coalesced rows).
+__global__ __launch_bounds__(256) void k_store_adjoint(const float2 *__restrict__ G, int rows,
+                                                       int Npad, const float4 *__restrict__ U,
+                                                       float4 *__restrict__ P) {
+  __shared__ float4 us[kStoreRows];
+  const int c = blockIdx.y;
+  const int r0 = c * kStoreRows;
+  const int rn = min(kStoreRows, rows - r0);
+  if (threadIdx.x < kStoreRows)
+    us[threadIdx.x] = threadIdx.x < rn ? U[r0 + threadIdx.x] : make_float4(0.f, 0.f, 0.f, 0.f);
+  __syncthreads();
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= Npad) return;
+  const float2 *g = G + static_cast<size_t>(r0) * Npad + m;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 16
+  for (int q = 0; q < rn; ++q) {
+    const float2 a = g[static_cast<size_t>(q) * Npad];
+    const float4 u = us[q];
+    // conj(a) * (u.x + i u.y), conj(a) * (u.z + i u.w)
+    acc.x = fmaf(a.x, u.x, fmaf(a.y, u.y, acc.x));
+    acc.y = fmaf(a.x, u.y, fmaf(-a.y, u.x, acc.y));
+    acc.z = fmaf(a.x, u.z, fmaf(a.y, u.w, acc.z));
+    acc.w = fmaf(a.x, u.w, fmaf(-a.y, u.z, acc.w));
+  }
+  P[static_cast<size_t>(c) * Npad + m] = acc;
+}
+
+__global__ void k_rotate(const float2 *__restrict__ d, int K, float cphi, float sphi,
+                         float2 *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) {
+    const float2 v = d[k];
+    // d e^{-i phi}
+    out[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
+  }
+}
+
+__global__ void k_scale(const float2 *__restrict__ x, float scale, int n, float2 *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2(x[i].x * scale, x[i].y * scale);
+}
+
 }  // namespace
+
+hipError_t launch_count_large(const float2 *c, int M, float thr, unsigned *count, hipStream_t st) {
+  int blocks = (M + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_count_large, dim3(blocks), dim3(256), 0, st, c, M, thr, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const float2 *x, float scale, int n, float2 *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3((n + 255) / 256), dim3(256), 0, st, x, scale, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (a.chunk == 2) {
@@ -356,10 +480,48 @@ hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, h
 }
 
 hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (a.P) {
+    if (a.nchunks < 1) return hipErrorInvalidValue;
+    if (t0)
+      hipExtLaunchKernelGGL(k_step_update<true>, dim3(a.nb * kUpdSplit), dim3(256), 0, st, t0, t1, 0, a);
+    else
+      hipLaunchKernelGGL(k_step_update<true>, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
+  } else if (t0) {
+    hipExtLaunchKernelGGL(k_step_update<false>, dim3(a.nb * kUpdSplit), dim3(256), 0, st, t0, t1, 0, a);
+  } else {
+    hipLaunchKernelGGL(k_step_update<false>, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_store_forward(const float2 *G, const float2 *D, int rows, int Npad, int M,
+                                const float2 *z, const float2 *w, float4 *U, hipStream_t st,
+                                hipEvent_t t0, hipEvent_t t1) {
+  if (rows <= 0) return hipSuccess;
+  const dim3 grid((rows + 3) / 4);
   if (t0)
-    hipExtLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, t0, t1, 0, a);
+    hipExtLaunchKernelGGL(k_store_forward, grid, dim3(256), 0, st, t0, t1, 0, G, D, rows, Npad, M, z,
+                          w, U);
   else
-    hipLaunchKernelGGL(k_step_update, dim3(a.nb * kUpdSplit), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_store_forward, grid, dim3(256), 0, st, G, D, rows, Npad, M, z, w, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_adjoint(const float2 *G, int rows, int Npad, const float4 *U, float4 *P,
+                                hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (rows <= 0) return hipSuccess;
+  const dim3 grid((Npad + 255) / 256, (rows + kStoreRows - 1) / kStoreRows);
+  if (t0)
+    hipExtLaunchKernelGGL(k_store_adjoint, grid, dim3(256), 0, st, t0, t1, 0, G, rows, Npad, U, P);
+  else
+    hipLaunchKernelGGL(k_store_adjoint, grid, dim3(256), 0, st, G, rows, Npad, U, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, float2 *out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_rotate, dim3((K + 255) / 256), dim3(256), 0, st, d, K,
+                     static_cast<float>(cos_c), static_cast<float>(sin_c), out);
   return hipGetLastError();
 }
 

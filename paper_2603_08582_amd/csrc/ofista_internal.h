@@ -91,6 +91,8 @@ struct DevState {
   int *tile_row0;    // index of tile (I, I)
   WorkItem *items;
   int *atom_ptr, *atom_pix, *pix_ptr, *pix_atom;  // edgelet tables (else NULL)
+  float2 *bp;        // BP accumulator, npix (NULL when not enabled)
+  unsigned *counter; // one word for ofista_count_large
   double2 *echo_tmp; // K clean-echo sums
   // split-BF16 operands of the Gram update, Npad x K words (NULL for FP32)
   unsigned *Ahi;
@@ -106,6 +108,9 @@ hipError_t launch_image(const Geom &g, const float2 *c, float2 *x, const DictTab
 // c = W^T x (adjoint of the image synthesis), padded to Npad.
 hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, const DictTabs &dt,
                                 hipStream_t st);
+// bp[p] += sum_k conj(F_s[k, p]) d_k e^{-i phi} for every pixel p.
+hipError_t launch_backproject(const Geom &g, const double *pos, int s, const float2 *d,
+                              double cos_c, double sin_c, float2 *bp, hipStream_t st);
 hipError_t launch_echo(const Geom &g, const double *pos, int s,
                        const float2 *rho, const float2 *noise, double snr_db,
                        double phase_err, double2 *tmp, float2 *out,
@@ -167,16 +172,37 @@ struct StepArgs {
   float2 *urec;  // if set, the update stores u = z - tau (H z - b) here
   int nb, N, nitems, chunk;
   float beta;
+  // store-all comparator: the update sums nchunks partial rows of P (stride
+  // Npad) instead of the tile-pass slots
+  const float4 *P;
+  int nchunks, Npad;
 };
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,
                              hipEvent_t t1 = nullptr);
 hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,
                               hipEvent_t t1 = nullptr);
+// Store-all comparator.  U[r] = (G_r z - D_r, G_r w) for the rows r < rows of
+// the stacked operator (rows x Npad, M used); P[c][m] = sum over rows
+// r in [64c, 64c + 64) of conj(G[r, m]) U[r]; then launch_step_update with
+// P set.  D: rows complex64 (the rotated data).
+constexpr int kStoreRows = 64;
+hipError_t launch_store_forward(const float2 *G, const float2 *D, int rows, int Npad, int M,
+                                const float2 *z, const float2 *w, float4 *U, hipStream_t st,
+                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_store_adjoint(const float2 *G, int rows, int Npad, const float4 *U, float4 *P,
+                                hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// out[k] = d[k] e^{-i phi}, k < K.
+hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, float2 *out,
+                         hipStream_t st);
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
                           int first, int rel, double lam_in, int lip,
                           int have_rho, const double *slot_r,
                           const double *slot_m, int nparts, hipStream_t st);
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
+// *count (zeroed by the caller) += #{m < M : |c_m| > thr} (FP32 magnitude).
+hipError_t launch_count_large(const float2 *c, int M, float thr, unsigned *count, hipStream_t st);
+// out[i] = x[i] * scale for i < n.
+hipError_t launch_scale(const float2 *x, float scale, int n, float2 *out, hipStream_t st);
 hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N,
                              int Npad, int nb, hipStream_t st);
 

@@ -405,6 +405,36 @@ __global__ __launch_bounds__(256) void k_image_adjoint_edgelet(int M, int Npad,
   c[m] = acc;
 }
 
+// BP accumulation (Section IV-A baseline): thread per pixel, the rotated
+// pulse staged in LDS; conj(F) = exp(+i 4 pi f R / c0) with the FP64 phase.
+__global__ __launch_bounds__(256) void k_backproject(Geom g, const double *__restrict__ pos, int s,
+                                                     const float2 *__restrict__ d, float cphi,
+                                                     float sphi, float2 *__restrict__ bp) {
+  extern __shared__ float2 dr[];  // K rotated samples
+  for (int k = threadIdx.x; k < g.K; k += 256) {
+    const float2 v = d[k];
+    // d e^{-i phi}
+    dr[k] = make_float2(v.x * cphi + v.y * sphi, v.y * cphi - v.x * sphi);
+  }
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= g.npix) return;
+  const double R = pixel_range(g, pos + 3 * s, p);
+  const double c4 = 4.0 * kPi / kC0;
+  float re = 0.f, im = 0.f;
+  for (int k = 0; k < g.K; ++k) {
+    const float2 f = phasor_neg((c4 * (g.f0 + k * g.df)) * R);  // F[k, p]
+    const float2 x = dr[k];
+    // conj(f) * x
+    re += f.x * x.x + f.y * x.y;
+    im += f.x * x.y - f.y * x.x;
+  }
+  float2 acc = bp[p];
+  acc.x += re;
+  acc.y += im;
+  bp[p] = acc;
+}
+
 constexpr int kKKB = 16;   // G block edge
 constexpr int kKKM = 64;   // coefficients staged per step
 
@@ -536,6 +566,14 @@ hipError_t launch_image_adjoint(const Geom &g, const float2 *x, float2 *c, const
   } else {
     hipLaunchKernelGGL(k_copy_pad_c64, dim3((g.Npad + 255) / 256), dim3(256), 0, st, x, c, g.N, g.Npad);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_backproject(const Geom &g, const double *pos, int s, const float2 *d,
+                              double cos_c, double sin_c, float2 *bp, hipStream_t st) {
+  const size_t lds = static_cast<size_t>(g.K) * sizeof(float2);
+  hipLaunchKernelGGL(k_backproject, dim3((g.npix + 255) / 256), dim3(256), lds, st, g, pos, s, d,
+                     static_cast<float>(cos_c), static_cast<float>(sin_c), bp);
   return hipGetLastError();
 }
 

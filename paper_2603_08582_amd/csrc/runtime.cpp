@@ -25,6 +25,12 @@ struct Layout {
   // N: coefficient count M (length of b, c, ...); npix: pixels
   int N = 0, Npad = 0, nb = 0, K = 0, npos = 0, chunk = 4, nparts = 0, npix = 0;
   size_t nnz = 0;  // edgelet: total pixels over all atoms
+  bool has_bp = false;
+  size_t bp = 0, counter = 0;
+  // store-all comparator: capacity, stacked rows, partial rows
+  bool store = false;
+  int store_cap = 0, store_chunks = 0;
+  size_t Gst = 0, Dst = 0, Ust = 0, Pst = 0;
   size_t atom_ptr = 0, atom_pix = 0, pix_ptr = 0, pix_atom = 0;
   size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
   // byte offsets
@@ -43,7 +49,8 @@ size_t state_record_bytes(const Layout &L) {
   return align_up(16 * sizeof(double)) + align_up(sizeof(DevScalars)) +
          2 * align_up(2 * L.nparts * sizeof(double)) +
          3 * align_up(static_cast<size_t>(L.Npad) * sizeof(float2)) +
-         L.ntiles * kTile * kTile * sizeof(float2);
+         align_up(L.ntiles * kTile * kTile * sizeof(float2)) +
+         (L.has_bp ? align_up(static_cast<size_t>(L.npix) * sizeof(float2)) : 0);
 }
 
 size_t count_items(int nb, int chunk) {
@@ -150,8 +157,11 @@ ofista_status check(const ofista_config *c, std::string *why) {
       return OFISTA_E_UNSUPPORTED;
     }
     // the per-position K x K FP64 matrices of sigma^2 borrow the H region
+    // (the stored-pulse region when storing pulses)
     const long long nbm = (M + kTile - 1) / kTile;
-    const long long hbytes = nbm * (nbm + 1) / 2 * kTile * kTile * 8;
+    const long long hbytes = c->storage == OFISTA_STORE_PULSES
+                                 ? static_cast<long long>(c->max_pulses) * c->n_freq * nbm * kTile * 8
+                                 : nbm * (nbm + 1) / 2 * kTile * kTile * 8;
     if (static_cast<long long>(c->n_freq) * c->n_freq * 16 > hbytes) {
       if (why) *why = "edgelet dictionary: K*K*16 bytes exceed the H storage";
       return OFISTA_E_UNSUPPORTED;
@@ -183,6 +193,14 @@ ofista_status check(const ofista_config *c, std::string *why) {
     return bad("recording needs max_pulses >= 1 and max_iters >= 1");
   for (int i = 0; i < 3 * c->n_pos; ++i)
     if (!std::isfinite(c->pos_xyz[i])) return bad("pos_xyz must be finite");
+  if (c->storage != OFISTA_STORE_GRAM && c->storage != OFISTA_STORE_PULSES) return bad("unknown storage");
+  if (c->storage == OFISTA_STORE_PULSES) {
+    if (c->max_pulses < 1) return bad("storing pulses needs max_pulses >= 1");
+    if (c->record_every != 0 || c->precision != OFISTA_PREC_FP32) {
+      if (why) *why = "storing pulses excludes recording and the split-BF16 Gram";
+      return OFISTA_E_UNSUPPORTED;
+    }
+  }
   return OFISTA_OK;
 }
 
@@ -194,7 +212,8 @@ Layout layout(const ofista_config *c) {
   L.Npad = L.nb * kTile;
   L.K = c->n_freq;
   L.npos = c->n_pos;
-  L.ntiles = static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
+  L.store = c->storage == OFISTA_STORE_PULSES;
+  L.ntiles = L.store ? 0 : static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
   L.ntiles_grid = (L.ntiles + 7) / 8 * 8;
   L.chunk = pick_chunk(L.nb);
   L.nparts = kUpdSplit * L.nb;
@@ -215,7 +234,16 @@ Layout layout(const ofista_config *c) {
   L.z1 = take(vec);
   L.w0 = take(vec);
   L.w1 = take(vec);
-  L.Q = take(static_cast<size_t>(L.nb) * L.nb * kTile * sizeof(float4));
+  L.Q = take(L.store ? 0 : static_cast<size_t>(L.nb) * L.nb * kTile * sizeof(float4));
+  if (L.store) {
+    L.store_cap = c->max_pulses;
+    const size_t rows = static_cast<size_t>(L.store_cap) * L.K;
+    L.store_chunks = static_cast<int>((rows + kStoreRows - 1) / kStoreRows);
+    L.Gst = take(rows * L.Npad * sizeof(float2));
+    L.Dst = take(rows * sizeof(float2));
+    L.Ust = take(rows * sizeof(float4));
+    L.Pst = take(static_cast<size_t>(L.store_chunks) * L.Npad * sizeof(float4));
+  }
   L.slot0 = take(2 * L.nparts * sizeof(double));
   L.slot1 = take(2 * L.nparts * sizeof(double));
   L.scal = take(sizeof(DevScalars));
@@ -226,6 +254,9 @@ Layout layout(const ofista_config *c) {
   L.tile_row0 = take(L.nb * sizeof(int));
   L.items = take(L.nitems * sizeof(WorkItem));
   L.echo_tmp = take(L.K * sizeof(double2));
+  L.counter = take(sizeof(unsigned));
+  L.has_bp = c->backprojection != 0;
+  if (L.has_bp) L.bp = take(static_cast<size_t>(L.npix) * sizeof(float2));
   if (c->dict == OFISTA_DICT_EDGELET) {
     L.atom_ptr = take((static_cast<size_t>(L.N) + 1) * sizeof(int));
     L.atom_pix = take(L.nnz * sizeof(int));
@@ -285,7 +316,9 @@ enum ProfClass {
   kProfCorr = 3,
   kProfScalars = 4,
   kProfUpdate = 5,
-  kProfN = 6
+  kProfStoreFwd = 6,
+  kProfStoreAdj = 7,
+  kProfN = 8
 };
 
 }  // namespace
@@ -295,6 +328,9 @@ struct ofista_ctx {
   Layout L;
   Geom g{};
   DictTabs dt{};
+  // store-all comparator buffers (NULL in the Gram mode)
+  float2 *Gst = nullptr, *Dst = nullptr;
+  float4 *Ust = nullptr, *Pst = nullptr;
   DevState d{};
   hipStream_t st = nullptr;
   int device = 0;
@@ -392,6 +428,7 @@ ofista_status do_reset(ofista_ctx *c) {
   }
   OF_CK(c, launch_fill(d.wbuf[1], vecw, 0u, c->st));
   OF_CK(c, launch_fill(d.scal, sizeof(DevScalars) / 4, 0u, c->st));
+  if (d.bp) OF_CK(c, launch_fill(d.bp, static_cast<size_t>(L.npix) * 2, 0u, c->st));
   OF_CK(c, launch_init_power(d.wbuf[0], d.slots[0], d.slots[1], L.N, L.Npad, L.nparts, c->st));
   c->n = 0;
   c->G = 0;
@@ -420,7 +457,7 @@ size_t ofista_workspace_bytes(const ofista_config *cfg) {
 }
 
 size_t ofista_state_bytes(const ofista_config *cfg) {
-  if (check(cfg, nullptr) != OFISTA_OK) return 0;
+  if (check(cfg, nullptr) != OFISTA_OK || cfg->storage == OFISTA_STORE_PULSES) return 0;
   return state_record_bytes(layout(cfg));
 }
 
@@ -488,6 +525,12 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   d.pix_ptr = edgelet ? reinterpret_cast<int *>(base + L.pix_ptr) : nullptr;
   d.pix_atom = edgelet ? reinterpret_cast<int *>(base + L.pix_atom) : nullptr;
   c->dt = DictTabs{cfg->dict, cfg->haar_levels, d.atom_ptr, d.atom_pix, d.pix_ptr, d.pix_atom};
+  d.counter = reinterpret_cast<unsigned *>(base + L.counter);
+  d.bp = L.has_bp ? reinterpret_cast<float2 *>(base + L.bp) : nullptr;
+  c->Gst = L.store ? reinterpret_cast<float2 *>(base + L.Gst) : nullptr;
+  c->Dst = L.store ? reinterpret_cast<float2 *>(base + L.Dst) : nullptr;
+  c->Ust = L.store ? reinterpret_cast<float4 *>(base + L.Ust) : nullptr;
+  c->Pst = L.store ? reinterpret_cast<float4 *>(base + L.Pst) : nullptr;
 
   // host tables
   const int nb = L.nb;
@@ -504,7 +547,7 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
     // over super-tiles, so that a run of the table touches few A blocks
     t = 0;
     constexpr int S = 8;
-    const int ns = (nb + S - 1) / S;
+    const int ns = L.store ? 0 : (nb + S - 1) / S;  // no Gram when storing pulses
     for (int P = 0; P < ns; ++P)
       for (int Qs = P; Qs < ns; ++Qs)
         for (int I = P * S; I < std::min(nb, P * S + S); ++I)
@@ -525,7 +568,8 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   if ((e = hipGetDevice(&c->device)) != hipSuccess) return fail(e, "hipGetDevice");
   if ((e = hipMemcpyAsync(d.pos, cfg->pos_xyz, 3 * sizeof(double) * L.npos, hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy positions");
-  if ((e = hipMemcpyAsync(d.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice, c->st)) != hipSuccess)
+  if (!tij.empty() &&
+      (e = hipMemcpyAsync(d.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy tile table");
   if ((e = hipMemcpyAsync(d.tile_row0, row0.data(), row0.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy tile rows");
@@ -550,8 +594,10 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
     // sigma^2 per position from the K x K FP64 matrix A_s A_s^H, in batches
     // that fit the (not yet used) H region
     const size_t per = static_cast<size_t>(L.K) * L.K;
-    const size_t batch = std::max<size_t>(1, (L.ntiles * kTile * kTile * sizeof(float2)) / (per * sizeof(double2)));
-    double2 *Gs = reinterpret_cast<double2 *>(d.H);
+    const size_t scratch = L.store ? static_cast<size_t>(L.store_cap) * L.K * L.Npad * sizeof(float2)
+                                   : L.ntiles * kTile * kTile * sizeof(float2);
+    const size_t batch = std::max<size_t>(1, scratch / (per * sizeof(double2)));
+    double2 *Gs = reinterpret_cast<double2 *>(L.store ? base + L.Gst : reinterpret_cast<char *>(d.H));
     for (int s0 = 0; s0 < L.npos; s0 += static_cast<int>(batch)) {
       const int nm = static_cast<int>(std::min<size_t>(batch, static_cast<size_t>(L.npos - s0)));
       for (int j = 0; j < nm; ++j) {
@@ -592,7 +638,10 @@ float2 *seg_ptr(ofista_ctx *c, size_t off, size_t idx, size_t stride) {
 // One pulse: rows, H and b updates, scalars.  seg_j >= 0 while the backward
 // pass re-runs pulse seg_j of a segment: then also keep H_n, Delta b_n and the
 // scalars of this pulse.
+ofista_status push_store(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr);
+
 ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr, int seg_j) {
+  if (c->L.store) return push_store(c, d_pulse, s, phase_corr);
   const DevState &d = c->d;
   const Layout &L = c->L;
   const int first = c->n == 0 ? 1 : 0;
@@ -600,6 +649,9 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
     ProfScope p(c, kProfRows);
     OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->dt, c->st));
   }
+  if (d.bp)
+    OF_CK(c, launch_backproject(c->g, d.pos, s, static_cast<const float2 *>(d_pulse),
+                                std::cos(phase_corr), std::sin(phase_corr), d.bp, c->st));
   if (seg_j >= 0) {
     OF_CK(c, launch_corr(c->g, d.A, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
                          std::sin(phase_corr), nullptr, d.scal, 0, c->st,
@@ -639,6 +691,39 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
   return OFISTA_OK;
 }
 
+// Store-all comparator: keep G_s = F_s W and the rotated data of pulse n in
+// slot n; lambda from Delta b_1 = G_1^H d~_1 (the correlation kernel with no
+// b), then the same scalars as the Gram mode.  b stays zero: the gradient
+// sum_k G_k^H (G_k z - d_k) already holds the data term.
+ofista_status push_store(ofista_ctx *c, const void *d_pulse, int32_t s, double phase_corr) {
+  const DevState &d = c->d;
+  const Layout &L = c->L;
+  if (c->n >= L.store_cap) return OFISTA_E_STATE;
+  const int first = c->n == 0 ? 1 : 0;
+  float2 *G = c->Gst + static_cast<size_t>(c->n) * L.K * L.Npad;
+  {
+    ProfScope p(c, kProfRows);
+    OF_CK(c, launch_rows(c->g, d.pos, s, G, c->dt, c->st));
+  }
+  if (d.bp)
+    OF_CK(c, launch_backproject(c->g, d.pos, s, static_cast<const float2 *>(d_pulse),
+                                std::cos(phase_corr), std::sin(phase_corr), d.bp, c->st));
+  OF_CK(c, launch_rotate(static_cast<const float2 *>(d_pulse), L.K, std::cos(phase_corr),
+                         std::sin(phase_corr), c->Dst + static_cast<size_t>(c->n) * L.K, c->st));
+  if (first)
+    OF_CK(c, launch_corr(c->g, G, static_cast<const float2 *>(d_pulse), std::cos(phase_corr),
+                         std::sin(phase_corr), nullptr, d.scal, 1, c->st));
+  {
+    ProfScope p(c, kProfScalars);
+    const int par = static_cast<int>(c->G & 1);
+    OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
+                            c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
+                            L.nparts, c->st));
+  }
+  c->n += 1;
+  return OFISTA_OK;
+}
+
 // Algorithm 1 with `iters` steps; seg_j >= 0 also keeps u of every step.
 ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, int seg_j,
                                double *t_start_out) {
@@ -673,7 +758,22 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.nitems = static_cast<int>(L.nitems);
     a.chunk = L.chunk;
     a.beta = static_cast<float>(beta);
-    {
+    if (L.store) {
+      // gradient from the n stored pulses: two passes over the stacked rows
+      const int rows = static_cast<int>(c->n) * L.K;
+      a.P = c->Pst;
+      a.nchunks = (rows + kStoreRows - 1) / kStoreRows;
+      a.Npad = L.Npad;
+      {
+        ProfScope ps(c, kProfStoreFwd, true);
+        OF_CK(c, launch_store_forward(c->Gst, c->Dst, rows, L.Npad, L.N, a.zc, a.wc, c->Ust, c->st,
+                                      ps.t0(), ps.t1()));
+      }
+      {
+        ProfScope ps(c, kProfStoreAdj, true);
+        OF_CK(c, launch_store_adjoint(c->Gst, rows, L.Npad, c->Ust, c->Pst, c->st, ps.t0(), ps.t1()));
+      }
+    } else {
       ProfScope ps(c, kProfStep, true);
       OF_CK(c, launch_step_tiles(a, c->st, ps.t0(), ps.t1()));
     }
@@ -837,6 +937,7 @@ ofista_status ofista_backward(ofista_ctx *c, const void *d_grad_img, double *gra
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   const Layout &L = c->L;
+  if (L.store) return OFISTA_E_UNSUPPORTED;
   if (L.rec_every <= 0) return OFISTA_E_STATE;
   if (!d_grad_img || !grad_lambda || !grad_phase) return OFISTA_E_ARG;
   const int P = static_cast<int>(c->n);
@@ -921,6 +1022,7 @@ ofista_status ofista_gram(ofista_ctx *c, void *d_out) {
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   if (!d_out) return OFISTA_E_ARG;
+  if (c->L.store) return OFISTA_E_UNSUPPORTED;      // no Gram is kept
   if (c->L.N > 16384) return OFISTA_E_UNSUPPORTED;  // inspection of small problems only
   OF_CK(c, launch_gram_dense(c->g, c->d.H, c->d.tile_row0, static_cast<float2 *>(d_out), c->st));
   return OFISTA_OK;
@@ -931,6 +1033,7 @@ ofista_status ofista_gram_entries(ofista_ctx *c, int32_t n, const int32_t *d_i, 
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   if (n < 0 || (n > 0 && (!d_i || !d_j || !d_out))) return OFISTA_E_ARG;
+  if (c->L.store) return OFISTA_E_UNSUPPORTED;
   OF_CK(c, launch_gram_entries(c->g, c->d.H, c->d.tile_row0, n, d_i, d_j,
                                static_cast<float2 *>(d_out), c->st));
   return OFISTA_OK;
@@ -945,6 +1048,30 @@ ofista_status ofista_echo(ofista_ctx *c, int32_t s, const void *d_rho, const voi
   OF_CK(c, launch_echo(c->g, c->d.pos, s, static_cast<const float2 *>(d_rho),
                        static_cast<const float2 *>(d_noise), snr_db, phase_err, c->d.echo_tmp,
                        static_cast<float2 *>(d_out), c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_bp_image(ofista_ctx *c, void *d_img_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!d_img_out) return OFISTA_E_ARG;
+  if (!c->d.bp || c->n == 0) return OFISTA_E_STATE;
+  OF_CK(c, launch_scale(c->d.bp, static_cast<float>(1.0 / static_cast<double>(c->n)), c->L.npix,
+                        static_cast<float2 *>(d_img_out), c->st));
+  return OFISTA_OK;
+}
+
+ofista_status ofista_count_large(ofista_ctx *c, double threshold, int64_t *count) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  if (!count || !std::isfinite(threshold)) return OFISTA_E_ARG;
+  OF_CK(c, launch_fill(c->d.counter, 1, 0u, c->st));
+  OF_CK(c, launch_count_large(c->d.cbuf[c->G & 1], c->L.N, static_cast<float>(threshold), c->d.counter,
+                              c->st));
+  unsigned h = 0;
+  OF_CK(c, hipMemcpyAsync(&h, c->d.counter, sizeof(unsigned), hipMemcpyDeviceToHost, c->st));
+  OF_CK(c, hipStreamSynchronize(c->st));
+  *count = static_cast<int64_t>(h);
   return OFISTA_OK;
 }
 
@@ -1011,6 +1138,9 @@ ofista_status export_to(ofista_ctx *c, void *d_buf) {
   OF_CK(c, hipMemcpyAsync(o, c->d.b, vec, hipMemcpyDeviceToDevice, c->st));
   o += align_up(vec);
   OF_CK(c, hipMemcpyAsync(o, c->d.H, L.ntiles * kTile * kTile * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(L.ntiles * kTile * kTile * sizeof(float2));
+  if (c->d.bp)
+    OF_CK(c, hipMemcpyAsync(o, c->d.bp, static_cast<size_t>(L.npix) * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
   OF_CK(c, hipStreamSynchronize(c->st));  // the header came from host stack memory
   return OFISTA_OK;
 }
@@ -1042,6 +1172,9 @@ ofista_status import_from(ofista_ctx *c, const void *d_buf) {
   OF_CK(c, hipMemcpyAsync(c->d.b, o, vec, hipMemcpyDeviceToDevice, c->st));
   o += align_up(vec);
   OF_CK(c, hipMemcpyAsync(c->d.H, o, L.ntiles * kTile * kTile * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+  o += align_up(L.ntiles * kTile * kTile * sizeof(float2));
+  if (c->d.bp)
+    OF_CK(c, hipMemcpyAsync(c->d.bp, o, static_cast<size_t>(L.npix) * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
   return OFISTA_OK;
 }
 
@@ -1053,6 +1186,7 @@ ofista_status ofista_export_state(ofista_ctx *c, void *d_buf) {
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   if (!d_buf) return OFISTA_E_ARG;
+  if (c->L.store) return OFISTA_E_UNSUPPORTED;
   return export_to(c, d_buf);
 }
 
@@ -1060,6 +1194,7 @@ ofista_status ofista_import_state(ofista_ctx *c, const void *d_buf) {
   ofista_status st = usable(c);
   if (st != OFISTA_OK) return st;
   if (!d_buf) return OFISTA_E_ARG;
+  if (c->L.store) return OFISTA_E_UNSUPPORTED;
   c->rec.clear();  // an imported state has no recorded history
   return import_from(c, d_buf);
 }

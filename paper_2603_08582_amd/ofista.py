@@ -21,7 +21,9 @@ DICT = {"identity": 0, "haar": 1, "edgelet": 2}
 PRECISION = {"fp32": 0, "split_bf16": 1}
 LIPSCHITZ = {"running": 0, "bound": 1}
 MOMENTUM = {"fista": 0, "restart": 1, "ista": 2}
-KERNEL = {"gram": 0, "step": 1, "rows": 2, "corr": 3, "scalars": 4, "update": 5}
+KERNEL = {"gram": 0, "step": 1, "rows": 2, "corr": 3, "scalars": 4, "update": 5,
+          "store_forward": 6, "store_adjoint": 7}
+STORAGE = {"gram": 0, "pulses": 1}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_RANGE", -3: "E_STATE", -4: "E_WORKSPACE",
           -5: "E_UNSUPPORTED", -6: "E_HIP"}
@@ -49,6 +51,7 @@ class OfistaConfig(ctypes.Structure):
         ("n_edge_lengths", ctypes.c_int32), ("edge_lengths", ctypes.POINTER(ctypes.c_int32)),
         ("n_edge_rotations", ctypes.c_int32),
         ("edge_rotations_deg", ctypes.POINTER(ctypes.c_double)),
+        ("backprojection", ctypes.c_int32), ("storage", ctypes.c_int32),
     ]
 
 
@@ -81,6 +84,8 @@ def lib() -> ctypes.CDLL:
         "ofista_reconstruct": (i32, [vp, i32, vp]),
         "ofista_image": (i32, [vp, vp]),
         "ofista_state": (i32, [vp, ctypes.POINTER(OfistaStats)]),
+        "ofista_bp_image": (i32, [vp, vp]),
+        "ofista_count_large": (i32, [vp, f64, ctypes.POINTER(ctypes.c_int64)]),
         "ofista_echo": (i32, [vp, i32, vp, vp, f64, f64, vp]),
         "ofista_rows": (i32, [vp, i32, vp]),
         "ofista_gram": (i32, [vp, vp]),
@@ -107,7 +112,8 @@ def lib() -> ctypes.CDLL:
 def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
                 dictionary="identity", haar_levels=0, lam=0.05, lam_relative=True,
                 precision="fp32", lipschitz="running", momentum="fista",
-                record_every=0, max_pulses=0, max_iters=0, edge_lengths=(), edge_rotations=()):
+                record_every=0, max_pulses=0, max_iters=0, edge_lengths=(), edge_rotations=(),
+                backprojection=False, storage="gram"):
     """Build an OfistaConfig; returns (config, keepalive) -- keep the second
     value alive while the config is in use (it owns the host tables)."""
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
@@ -123,7 +129,8 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
         record_every=record_every, max_pulses=max_pulses, max_iters=max_iters,
         n_edge_lengths=lens.size, edge_lengths=lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         n_edge_rotations=rots.size,
-        edge_rotations_deg=rots.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        edge_rotations_deg=rots.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        backprojection=1 if backprojection else 0, storage=STORAGE[storage])
     return cfg, (pos, lens, rots)
 
 
@@ -214,6 +221,18 @@ class OnlineFista:
         o = self._out(out, self.N)
         self._check(self._lib.ofista_image(self._ctx, _ptr(o)))
         return o
+
+    def bp_image(self, out=None):
+        """BP baseline: (1/n) sum of F_s^H d_s over the pushed pulses (pixels)."""
+        o = self._out(out, self.N)
+        self._check(self._lib.ofista_bp_image(self._ctx, _ptr(o)))
+        return o
+
+    def count_large(self, threshold: float = 2e-2) -> int:
+        """Number of coefficients with |c| > threshold (synchronises)."""
+        n = ctypes.c_int64()
+        self._check(self._lib.ofista_count_large(self._ctx, float(threshold), ctypes.byref(n)))
+        return int(n.value)
 
     def state(self) -> dict:
         s = OfistaStats()

@@ -162,3 +162,29 @@ def test_edgelet_workspace_grows_with_the_atom_count():
     a, ka = edgelet_cfg(16, (4,), (0.0,))
     b, kb = edgelet_cfg(16, (4,), (0.0, 90.0))
     assert ofista.workspace_bytes(b) > ofista.workspace_bytes(a) > 0
+
+
+def test_store_all_workspace_grows_with_capacity():
+    """Store-all keeps n pulses (K x M complex64 rows each) instead of the M x M
+    Gram: its workspace grows linearly with the capacity, by at least the
+    K x M operator per pulse; the Gram mode fits in the FP32 bytes of Table
+    I's Online FISTA count (it keeps only the upper triangle of H)."""
+    from oracle import memory
+    from paper_2603_08582_amd import ofista
+    from workload import library_kwargs, make_workload, spec
+    wl = make_workload(spec("small", n_side=32, patch_m=30.0, n_freq=64, n_points=2))
+    gram, kg = ofista.make_config(**library_kwargs(wl))
+    ws_gram = ofista.workspace_bytes(gram)
+    assert ws_gram <= 4 * memory.online_values(1024, 1024)
+    sizes = []
+    for cap in range(1, 41):
+        c, k = ofista.make_config(**library_kwargs(wl, storage="pulses", max_pulses=cap))
+        sizes.append(ofista.workspace_bytes(c))
+    steps = np.diff(sizes)
+    assert np.all(steps >= 64 * 1024 * 8) and np.ptp(steps) <= 4096
+    assert sizes[0] < ws_gram < sizes[-1]
+    bad, kb = ofista.make_config(**library_kwargs(wl, storage="pulses", max_pulses=0))
+    assert ofista.check_config(bad) == -1
+    rec, kr = ofista.make_config(**library_kwargs(wl, storage="pulses", max_pulses=4,
+                                                  record_every=2, max_iters=3))
+    assert ofista.check_config(rec) == -5
