@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the metric: time one pulse (push + m steps) at growing n "
+                         "for the Gram (Online FISTA) and the stored-pulse comparator, with "
+                         "their workspace sizes (Table I), as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of "
@@ -98,6 +102,8 @@ def main():
     from workload import library_kwargs, make_workload
 
     wl = make_workload(args.workload)
+    if args.table1:
+        return table1(wl, args)
     s = wl.spec
     N, K, P, m = s.n_pixels, s.n_freq, s.n_pulses, s.inner_steps
     dev = torch.device("cuda:0")
@@ -230,6 +236,52 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses, sched if session_mode else None)
+    print(json.dumps(out), flush=True)
+
+
+def table1(wl, args):
+    """Section III-D / Table I comparison on one GPU: for n = 1, 2, 4, ... up to
+    the workload's pulse count, the time of pulse n (push + m FISTA steps) and
+    the workspace of each method holding n pulses."""
+    import torch
+    from paper_2603_08582_amd import OnlineFista, workspace_bytes
+    from paper_2603_08582_amd.ofista import make_config
+    from workload import library_kwargs
+    s = wl.spec
+    P, K, m = s.n_pulses, s.n_freq, s.inner_steps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ns = sorted({1 << i for i in range(P.bit_length()) if (1 << i) <= P} | {P})
+    out = {"table1": s.name, "K": K, "inner_steps": m, "n": ns, "gram": {}, "pulses": {}}
+    rho = torch.from_numpy(wl.rho.astype(np.complex64)).to(dev)
+    noise = torch.from_numpy(wl.noise.astype(np.complex64)).to(dev)
+    for mode in ("gram", "pulses"):
+        kw = library_kwargs(wl, storage=mode, max_pulses=P) if mode == "pulses" else library_kwargs(wl)
+        g = OnlineFista(device=dev, **kw)
+        d = torch.empty((P, K), dtype=torch.complex64, device=dev)
+        for p in range(P):
+            g.echo(p, rho, noise[p], s.snr_db, float(wl.phase_err[p]), out=d[p])
+        times, mem = [], []
+        for n in ns:
+            g.reset()
+            for p in range(n - 1):
+                g.push_pulse(d[p], p)
+                g.reconstruct(m, copy=False)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(g.stream)
+            g.push_pulse(d[n - 1], n - 1)
+            g.reconstruct(m, copy=False)
+            t1.record(g.stream)
+            torch.cuda.synchronize()
+            times.append(t0.elapsed_time(t1))
+            cfg = make_config(**(library_kwargs(wl, storage=mode, max_pulses=n) if mode == "pulses"
+                                 else library_kwargs(wl)))[0]
+            mem.append(workspace_bytes(cfg))
+        out[mode] = {"ms_per_pulse": times, "workspace_bytes": mem, "M": g.M}
+        g.close()
+        del d
     print(json.dumps(out), flush=True)
 
 
