@@ -161,3 +161,27 @@ def test_full_size_edgelet64_sampled():
     assert np.max(np.abs(Hs - ref_H)) <= 1e-5 * np.max(np.abs(ref_H))
     b = host(g.vector("b"))[cols]
     assert rel(b, ref_b) < 1e-5
+
+
+@pytest.mark.parametrize("kw", [dict(precision="split_bf16"), dict(lipschitz="bound"),
+                                dict(momentum="restart")])
+def test_edgelet_with_other_modes(kw):
+    """The edgelet dictionary through the split-BF16 Gram (image tolerance
+    1e-3), the BOUND step rule and momentum restart (1e-4)."""
+    wl = make_workload(edge_spec(16, (4,), (0.0, 90.0), n_pulses=8))
+    d = sar.echoes(wl).astype(np.complex64)
+    g = gpu(wl, **kw)
+    okw = {"lip": kw["lipschitz"]} if "lipschitz" in kw else {}
+    if "momentum" in kw:
+        okw["momentum"] = kw["momentum"]
+    o = OnlineFistaOracle.from_workload(wl, **okw)
+    dd = dev(d)
+    for p in range(wl.spec.n_pulses):
+        g.push_pulse(dd[p], p)
+        g.reconstruct(wl.spec.inner_steps, copy=False)
+        o.push_pulse(d[p].astype(np.complex128), p)
+        o.reconstruct(wl.spec.inner_steps)
+    err = rel(host(g.image()), o.image())
+    tol = 1e-3 if kw.get("precision") == "split_bf16" else 1e-4
+    print(f"edgelet {kw}: image {err:.2e}")
+    assert err < tol
