@@ -423,6 +423,138 @@ __global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles
   }
 }
 
+// Split-BF16 Gram over 2 x 2 blocks of tiles: wave w owns the whole 64 x 64
+// tile (I0 + w/2, J0 + w%2) as 2 x 2 quadrants, so every A fragment read from
+// LDS feeds two quadrants and every B fragment two: half the LDS reads per
+// MFMA of the one-quadrant-per-wave layout.
+constexpr int kBbKB = 16;              // frequencies per stage
+constexpr int kBbStride = kBbKB + 4;   // words per column in LDS
+__global__ __launch_bounds__(256) void k_gram_bf16_blk(int K, int Npad, int nbB,
+                                                       const unsigned *__restrict__ Ahi,
+                                                       const unsigned *__restrict__ Alo,
+                                                       const int2 *__restrict__ blocks,
+                                                       float2 *__restrict__ H) {
+  __shared__ unsigned sAh[2 * kTile * kBbStride], sAl[2 * kTile * kBbStride];
+  __shared__ unsigned sBh[2 * kTile * kBbStride], sBl[2 * kTile * kBbStride];
+  const int2 blk = blocks[blockIdx.x];
+  const int IB = blk.x, JB = blk.y;
+  const int nb = Npad / kTile;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = wave >> 1, tj = wave & 1;
+  const int I = 2 * IB + ti, J = 2 * JB + tj;
+  const bool live = I < nb && J < nb && J >= I;
+  const int li = lane & 31, h = lane >> 5;
+  floatx16 acc[2][2][2];  // [qi][qj][Re, Im]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc[a][b][0][r] = 0.f;
+        acc[a][b][1][r] = 0.f;
+      }
+  // staging: per plane 128 columns x 16 frequencies = 512 u32x4; thread t
+  // loads columns (t >> 2) and (t >> 2) + 64, frequency quad t & 3
+  const u32x4 *gAh = reinterpret_cast<const u32x4 *>(Ahi);
+  const u32x4 *gAl = reinterpret_cast<const u32x4 *>(Alo);
+  const int Kq = K >> 2;
+  const int c0 = threadIdx.x >> 2, fq = threadIdx.x & 3;
+  auto colA = [&](int r) { return min(2 * IB * kTile + c0 + 64 * r, Npad - 1); };
+  auto colB = [&](int r) { return min(2 * JB * kTile + c0 + 64 * r, Npad - 1); };
+  u32x4 pah[2], pal[2], pbh[2], pbl[2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const size_t oA = static_cast<size_t>(colA(r)) * Kq + (k0 >> 2) + fq;
+      const size_t oB = static_cast<size_t>(colB(r)) * Kq + (k0 >> 2) + fq;
+      pah[r] = gAh[oA];
+      pal[r] = gAl[oA];
+      pbh[r] = gAh[oB];
+      pbl[r] = gAl[oB];
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int o = (c0 + 64 * r) * kBbStride + 4 * fq;
+      *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
+      *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
+      *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
+      *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += kBbKB) {
+    const bool more = k0 + kBbKB < K;
+    if (more) fetch(k0 + kBbKB);
+    if (live) {
+#pragma unroll
+      for (int g = 0; g < kBbKB / 8; ++g) {
+        bf16x8 Ah[2], Al[2], Bh[2], Bl[2], Bhi[2], Bli[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int oa = (ti * kTile + 32 * q + li) * kBbStride + 8 * g + 4 * h;
+          const int ob = (tj * kTile + 32 * q + li) * kBbStride + 8 * g + 4 * h;
+          const u32x4 ah = *reinterpret_cast<const u32x4 *>(&sAh[oa]);
+          const u32x4 al = *reinterpret_cast<const u32x4 *>(&sAl[oa]);
+          const u32x4 bh = *reinterpret_cast<const u32x4 *>(&sBh[ob]);
+          const u32x4 bl = *reinterpret_cast<const u32x4 *>(&sBl[ob]);
+          Ah[q] = as_bf16x8(ah);
+          Al[q] = as_bf16x8(al);
+          Bh[q] = as_bf16x8(bh);
+          Bl[q] = as_bf16x8(bl);
+          Bhi[q] = as_bf16x8(im_operand(bh));
+          Bli[q] = as_bf16x8(im_operand(bl));
+        }
+#pragma unroll
+        for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+          for (int qj = 0; qj < 2; ++qj) {
+            floatx16 &R = acc[qi][qj][0], &Im = acc[qi][qj][1];
+            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bh[qj], R, 0, 0, 0);
+            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bhi[qj], Im, 0, 0, 0);
+            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bl[qj], R, 0, 0, 0);
+            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bli[qj], Im, 0, 0, 0);
+            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[qi], Bh[qj], R, 0, 0, 0);
+            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[qi], Bhi[qj], Im, 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
+  float2 *Ht = H + tile_index * (kTile * kTile);
+#pragma unroll
+  for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj) {
+      float2 hv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * qi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        hv[r] = Ht[row * kTile + 32 * qj + li];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * qi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = 32 * qj + li;
+        hv[r].x += acc[qi][qj][0][r];
+        hv[r].y += acc[qi][qj][1][r];
+        if (I == J && row == col) hv[r].y = 0.f;
+        Ht[row * kTile + col] = hv[r];
+      }
+    }
+}
+
+
 // Dense N x N copy of the packed Hermitian H (inspection only).
 __global__ __launch_bounds__(256) void k_gram_dense(int N, int nb, const float2 *__restrict__ H,
                                                     const int *__restrict__ tile_row0,
@@ -488,11 +620,23 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
 }
 
 hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
-                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st,
-                              hipEvent_t t0, hipEvent_t t1) {
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, const int2 *blocks,
+                              int nblocks, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (g.K % kBfKB != 0) return hipErrorInvalidValue;
   dim3 sgrid(g.Npad / kSplitTile, (g.K + kSplitTile - 1) / kSplitTile);
   hipLaunchKernelGGL(k_split_bf16, sgrid, dim3(256), 0, st, g.K, g.Npad, A, Ahi, Alo);
+  if (blocks) {  // 2 x 2 tile blocks, one 64 x 64 tile per wave
+    const int nbB = (g.Npad / kTile + 1) / 2;
+    if (t0)
+      hipExtLaunchKernelGGL(k_gram_bf16_blk, dim3(nblocks), dim3(256), 0, st, t0, t1, 0, g.K, g.Npad,
+                            nbB, static_cast<const unsigned *>(Ahi), static_cast<const unsigned *>(Alo),
+                            blocks, H);
+    else
+      hipLaunchKernelGGL(k_gram_bf16_blk, dim3(nblocks), dim3(256), 0, st, g.K, g.Npad, nbB,
+                         static_cast<const unsigned *>(Ahi), static_cast<const unsigned *>(Alo),
+                         blocks, H);
+    return hipGetLastError();
+  }
   if (t0)  // the events time the product kernel only
     hipExtLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles_grid), dim3(256), 0, st, t0, t1, 0, g.K,
                           g.Npad, ntiles_grid, static_cast<const unsigned *>(Ahi),

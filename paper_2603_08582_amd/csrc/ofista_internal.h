@@ -133,9 +133,13 @@ hipError_t launch_corr(const Geom &g, const float2 *A, const float2 *d,
 // pixel-major hi/lo planes, then H += A^H A from three BF16 products.
 // Launchers of the timed kernels take optional events (t0, t1): when given,
 // they bracket that one kernel's execution (hipExtLaunchKernelGGL).
+// With blocks (nblocks 2 x 2 tile blocks (IB, JB), IB <= JB) the product runs
+// one 64 x 64 tile per wave over those blocks (same sums, fewer LDS reads per
+// MFMA, used for large N); otherwise one tile per workgroup over tile_ij.
 hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, unsigned *Alo,
-                              float2 *H, const int2 *tile_ij, int ntiles_grid, hipStream_t st,
-                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                              float2 *H, const int2 *tile_ij, int ntiles_grid, const int2 *blocks,
+                              int nblocks, hipStream_t st, hipEvent_t t0 = nullptr,
+                              hipEvent_t t1 = nullptr);
 // Correlation fused into the Gram update: b += A^H (d e^{-i phi}).
 struct CorrArgs {
   const float2 *d;

@@ -31,6 +31,8 @@ struct Layout {
   bool store = false;
   int store_cap = 0, store_chunks = 0;
   size_t Gst = 0, Dst = 0, Ust = 0, Pst = 0;
+  // split-BF16 Gram over 2 x 2 tile blocks (large N)
+  size_t bf_blocks = 0, nbf_blocks = 0;
   size_t atom_ptr = 0, atom_pix = 0, pix_ptr = 0, pix_atom = 0;
   size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
   // byte offsets
@@ -113,6 +115,11 @@ long long coef_count(const ofista_config *c, size_t *nnz) {
   if (nnz) *nnz = pix.size();
   return M;
 }
+
+// The split-BF16 Gram switches to 2 x 2 tile blocks (one tile per wave) from
+// this many tile rows on: measured faster at N = 16384 and 65536, slower at
+// N = 4096.
+constexpr int kBfBlockMinNb = 256;
 
 // Run length of the FISTA work items.  Runs of 2 tiles measured faster than
 // runs of 4 or 8 at both N = 4096 and N = 16384 (more workgroups in flight).
@@ -264,6 +271,11 @@ Layout layout(const ofista_config *c) {
     L.pix_atom = take(L.nnz * sizeof(int));
   }
   L.Ahi = L.Alo = 0;
+  if (c->precision == OFISTA_PREC_SPLIT_BF16 && L.nb >= kBfBlockMinNb) {
+    const size_t nbB = (L.nb + 1) / 2;
+    L.nbf_blocks = nbB * (nbB + 1) / 2;
+    L.bf_blocks = take(L.nbf_blocks * sizeof(int2));
+  }
   if (c->precision == OFISTA_PREC_SPLIT_BF16) {
     L.Ahi = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
     L.Alo = take(static_cast<size_t>(L.Npad) * L.K * sizeof(unsigned));
@@ -330,6 +342,7 @@ struct ofista_ctx {
   DictTabs dt{};
   // store-all comparator buffers (NULL in the Gram mode)
   float2 *Gst = nullptr, *Dst = nullptr;
+  const int2 *bf_blocks = nullptr;  // split-BF16 block table (large N), else NULL
   float4 *Ust = nullptr, *Pst = nullptr;
   DevState d{};
   hipStream_t st = nullptr;
@@ -553,6 +566,18 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
         for (int I = P * S; I < std::min(nb, P * S + S); ++I)
           for (int J = std::max(I, Qs * S); J < std::min(nb, Qs * S + S); ++J) tij[t++] = make_int2(I, J);
   }
+  std::vector<int2> bfb;
+  if (L.nbf_blocks) {
+    // 4 x 4 super-blocks, row-major over super-blocks
+    const int nbB = (nb + 1) / 2, S = 4, ns = (nbB + S - 1) / S;
+    bfb.reserve(L.nbf_blocks);
+    for (int P = 0; P < ns; ++P)
+      for (int Qs = P; Qs < ns; ++Qs)
+        for (int IB = P * S; IB < std::min(nbB, P * S + S); ++IB)
+          for (int JB = std::max(IB, Qs * S); JB < std::min(nbB, Qs * S + S); ++JB)
+            bfb.push_back(make_int2(IB, JB));
+    c->bf_blocks = reinterpret_cast<const int2 *>(base + L.bf_blocks);
+  }
   std::vector<WorkItem> items;
   items.reserve(L.nitems);
   for (int I = 0; I < nb; ++I)
@@ -573,6 +598,10 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
     return fail(e, "copy tile table");
   if ((e = hipMemcpyAsync(d.tile_row0, row0.data(), row0.size() * sizeof(int), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy tile rows");
+  if (!bfb.empty() &&
+      (e = hipMemcpyAsync(const_cast<int2 *>(c->bf_blocks), bfb.data(), bfb.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy block table");
   if ((e = hipMemcpyAsync(d.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy work items");
   std::vector<int> aptr, apix, pptr, patom;
@@ -665,7 +694,8 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
     }
     ProfScope p(c, kProfGram, true);
     OF_CK(c, launch_gram_bf16x3(c->g, d.A, d.Ahi, d.Alo, d.H, d.tile_ij,
-                                static_cast<int>(L.ntiles_grid), c->st, p.t0(), p.t1()));
+                                static_cast<int>(L.ntiles_grid), c->bf_blocks,
+                                static_cast<int>(L.nbf_blocks), c->st, p.t0(), p.t1()));
   } else {
     ProfScope p(c, kProfGram, true);
     CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
