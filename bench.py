@@ -108,7 +108,11 @@ def main():
     N, K, P, m = s.n_pixels, s.n_freq, s.n_pulses, s.inner_steps
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    g = OnlineFista(device=dev, **library_kwargs(wl))
+    # the differentiation form (record_every > 0): one step is the forward run
+    # with checkpoints plus the reverse pass for dL/dlambda and dL/dphases
+    diff_mode = s.record_every > 0
+    g = OnlineFista(device=dev, **(library_kwargs(wl, record_every=s.record_every, max_pulses=P,
+                                                  max_iters=m) if diff_mode else library_kwargs(wl)))
     stream = g.stream
 
     # a collection session (Section IV-A): Bernoulli-selected positions and an
@@ -138,9 +142,42 @@ def main():
         del src, dst
 
     pulses_per_step = [P]
+    if diff_mode:
+        target = torch.from_numpy(np.abs(wl.rho).astype(np.float32)).to(dev)
+        phases = np.zeros(P)
+        g.reset()
+        g.push_pulse(d[0], 0)
+        torch.cuda.synchronize()
+        lam_abs = g.state()["lam"]   # lambda of the relative rule, then held as an absolute value
+        diff_split = {"forward_ms": 0.0, "loss_ms": 0.0, "backward_ms": 0.0, "n": 0}
 
     def step():
         g.reset()
+        if diff_mode:
+            # forward: the recorded online run at the absolute lambda
+            g.set_lambda(lam_abs)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for p in range(P):
+                g.push_pulse(d[p], p, float(phases[p]))
+                g.reconstruct(m, copy=False)
+            e1.record(stream)
+            x = g.image()
+            # gradient of sum (|x| - |rho|)^2 (the caller's loss, plain tensor ops)
+            mag = x.abs()
+            gx = (2.0 * (mag - target) / mag.clamp_min(1e-30)) * x
+            em = torch.cuda.Event(enable_timing=True)
+            em.record(stream)
+            g.backward(gx.contiguous())
+            e2.record(stream)
+            torch.cuda.synchronize()
+            diff_split["forward_ms"] += e0.elapsed_time(e1)
+            diff_split["loss_ms"] += e1.elapsed_time(em)
+            diff_split["backward_ms"] += em.elapsed_time(e2)
+            diff_split["n"] += 1
+            return
         if session_mode:
             res = sess.run_session(g, d, sched, m, ideal=s.ideal_count, threshold=s.large_thresh)
             pulses_per_step[0] = len(res["pushed"])
@@ -152,6 +189,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if diff_mode:  # the split covers the timed steps only (the first run loads code)
+        diff_split.update(forward_ms=0.0, loss_ms=0.0, backward_ms=0.0, n=0)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
@@ -160,6 +199,8 @@ def main():
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
+    if diff_mode:
+        diff_timed = dict(diff_split)
 
     # per-kernel durations: the same steps again with HIP events around every
     # launch of the Gram update and of the FISTA step (library stream)
@@ -234,6 +275,17 @@ def main():
         "roofline_dominant_detail": {"avg_ms": dominant["avg_ms"], "launches": dominant["launches"]},
         "image_finite": finite,
     }
+    if diff_mode:
+        n = max(diff_timed["n"], 1)
+        out["differentiation"] = {
+            "gradients_per_s": 1e3 / ms, "forward_ms": diff_timed["forward_ms"] / n,
+            "loss_ms": diff_timed["loss_ms"] / n,
+            "backward_ms": diff_timed["backward_ms"] / n,
+            "backward_over_forward": diff_timed["backward_ms"] / max(diff_timed["forward_ms"], 1e-9),
+            "checkpoint_every": s.record_every,
+            "what": "one step = recorded forward over all pulses (forward_ms) + image and loss "
+                    "gradient (loss_ms) + reverse pass for dL/dlambda and dL/dphase with "
+                    "L = sum(|x| - |rho|)^2 (backward_ms)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses, sched if session_mode else None)
     print(json.dumps(out), flush=True)
