@@ -186,11 +186,11 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
   }
 }
 
-constexpr int kCorrPix = 64;    // pixels per workgroup
-constexpr int kCorrGroups = 4;  // frequency groups per workgroup (k = g, g+4, ...)
+constexpr int kCorrPix = 32;    // pixels per workgroup
+constexpr int kCorrGroups = 8;  // frequency groups per workgroup (k = g, g+8, ...)
 
 // b += A^H (d e^{-i phi}); at the first pulse also max_i |Delta b_i| for
-// lambda.  Workgroup = 64 pixels x 4 frequency groups; the 4 group sums are
+// lambda.  Workgroup = 32 pixels x 8 frequency groups; the 8 group sums are
 // added in fixed order.
 __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__ A,
                                               const float2 *__restrict__ d,
@@ -211,6 +211,7 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__
   const int grp = threadIdx.x / kCorrPix;
   const int i = blockIdx.x * kCorrPix + px;  // < Npad (Npad is a multiple of 64)
   float re = 0.f, im = 0.f;
+#pragma unroll 8
   for (int k = grp; k < g.K; k += kCorrGroups) {
     const float2 a = A[static_cast<size_t>(k) * g.Npad + i];
     const float2 x = dl[k];
