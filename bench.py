@@ -94,7 +94,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of "
-              "Online FISTA is described in DESIGN.md but not built", file=sys.stderr)
+              "Online FISTA (row blocks of H per GPU, one exchange of z per step) is a design, "
+              "not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -281,7 +281,7 @@ void ofista_destroy(struct ofista_ctx *ctx);
 /* Static message for a status; with a ctx, the last detailed message. */
 const char *ofista_error_string(const struct ofista_ctx *ctx, ofista_status st);
 
-/* Layout constants of this build (for tests): tile edge of the packed
+/* Layout constants of the library (for tests): tile edge of the packed
    Hermitian storage. */
 int32_t ofista_tile(void);
 

@@ -13,7 +13,7 @@ adjoint-imaged pulses, (1/n) sum_k F_k^H d_k in the pixel domain, shown in dB
 as 20 log10 of its magnitude.
 
 Section IV-B's SNR is 20 log10(mu_signal / mu_noise) with mu the power of
-signal and noise (printed that way; see the reading in the design doc): here mu_signal
+signal and noise (printed that way, although both are powers): here mu_signal
 is the mean |x|^2 over the true scene support and mu_noise the mean |x|^2
 over the remaining pixels.
 

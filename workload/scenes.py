@@ -15,7 +15,7 @@ m inner steps per pulse) at the sizes of the five benchmark configurations:
                  collection of Section IV-A), Bernoulli pulse selection, K=64,
                  edgelets (length 4, 0 and 90 deg), one square target
 
-Readings of details the paper leaves open (all listed in the design doc):
+Readings of details the paper leaves open:
 
 * pixel grid is cell-centred on a flat (z = 0) patch centred at the origin;
   pixel (iy, ix) sits at (-W/2 + (ix + 1/2) dx, -W/2 + (iy + 1/2) dx, 0) and has
