@@ -67,13 +67,13 @@ __global__ __launch_bounds__(256) void k_adj_update(AdjArgs a) {
   const int t = threadIdx.x;
   const int r = t & 63, part = t >> 6;
   float2 acc = make_float2(0.f, 0.f);
-  const float4 *q = a.Q + static_cast<size_t>(R) * nb * kTile + r;
+  const float4 *q = a.Q + r;
   for (int j0 = part; j0 < nb; j0 += 4 * kAdjBatch) {
     float4 v[kAdjBatch];
 #pragma unroll
     for (int u = 0; u < kAdjBatch; ++u) {
       const int j = j0 + 4 * u;
-      v[u] = q[static_cast<size_t>(j < nb ? j : nb - 1) * kTile];
+      v[u] = q[slot_index(j < nb ? j : nb - 1, R, nb) * kTile];
     }
 #pragma unroll
     for (int u = 0; u < kAdjBatch; ++u) {

@@ -19,6 +19,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // the nb(nb+1)/2 tiles (I, J), I <= J, of a zero-padded Npad x Npad matrix
 // (Npad = nb * kTile), each tile row-major, tiles in row-major upper order.
 constexpr int kTile = 64;
+
+// Slot of the matvec partials (nb x nb slots of kTile float4) that holds the
+// contribution of source tile row/column v to target tile row R.  Row partials
+// (v >= R, the run start of tile row R) sit at [R][v], the upper part
+// including the diagonal.  Column partials (v < R, from tile (v, R)) sit at
+// [nb-1-v][nb-1-R], strictly below the diagonal, so the column partials one
+// work item writes are adjacent and those of one source row are contiguous.
+__host__ __device__ inline size_t slot_index(int v, int R, int nb) {
+  return v >= R ? static_cast<size_t>(R) * nb + v
+                : static_cast<size_t>(nb - 1 - v) * nb + (nb - 1 - R);
+}
 // Tiles per FISTA work item (a run of tiles along one tile row): 2 or 4.
 constexpr int kChunk = 2;
 // Workgroups per tile row in the FISTA update; the power-iteration parts

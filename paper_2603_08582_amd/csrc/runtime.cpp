@@ -578,11 +578,17 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
             bfb.push_back(make_int2(IB, JB));
     c->bf_blocks = reinterpret_cast<const int2 *>(base + L.bf_blocks);
   }
+  // Full runs first, then the short last runs of the rows: the short items
+  // then fill the tail of the pass instead of delaying full ones (-3% at
+  // N = 4096, neutral at 16384).  Slots depend on (I, J0) only, so the order
+  // does not change any result.
   std::vector<WorkItem> items;
   items.reserve(L.nitems);
   for (int I = 0; I < nb; ++I)
     for (int J0 = I; J0 < nb; J0 += L.chunk)
       items.push_back(WorkItem{I, J0, J0 + L.chunk < nb ? J0 + L.chunk : nb, 0});
+  std::stable_partition(items.begin(), items.end(),
+                        [&](const WorkItem &w) { return w.J1 - w.J0 == L.chunk; });
 
   auto fail = [&](hipError_t e, const char *where) {
     fail_hip(c, e, where);
