@@ -26,11 +26,16 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // (b % 8) * per + b / 8 gives each XCD a contiguous run of the tile table,
 // whose order (8 x 8 super-tiles) keeps the A blocks of concurrently running
 // tiles inside one XCD's L2.
+//
+// A table entry with a nonzero piece number p is part p of a split tile: it
+// contracts only frequency stages [(p-1) nst / parts, p nst / parts) of the
+// nst stages and stores its partial to P instead of updating H.
 template <int KB>
 __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_grid,
                                                    const float2 *__restrict__ A,
                                                    const int2 *__restrict__ tile_ij,
-                                                   float2 *__restrict__ H, CorrArgs corr) {
+                                                   float2 *__restrict__ H, CorrArgs corr,
+                                                   float2 *__restrict__ P, int parts) {
   static_assert(KB % 8 == 0, "two float4 loads per thread per 8 frequencies");
   constexpr int kLoads = KB / 8;  // float4 per thread per operand and step
   __shared__ float2 sa[KB][kTile];
@@ -40,7 +45,14 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
   const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int2 ij = tile_ij[logical];
   if (ij.x < 0) return;  // padding of the grid to a multiple of 8
-  const int I = ij.x, J = ij.y;
+  const int I = ij.x & 0xFFFF, J = ij.y & 0xFFFFF;
+  const int piece = ij.y >> 20, sidx = ij.x >> 16;
+  int kbeg = 0, kend = K;
+  if (piece > 0) {
+    const int nst = (K + KB - 1) / KB;
+    kbeg = (piece - 1) * nst / parts * KB;
+    kend = min(K, piece * nst / parts * KB);
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = wave >> 1, wj = wave & 1;
   const bool hi = lane >= 32;
@@ -76,8 +88,8 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
   float4 pa[kLoads], pb[kLoads];
 #pragma unroll
   for (int r = 0; r < kLoads; ++r) {
-    const int k = kk0 + 8 * r;
-    const bool in = k < K;
+    const int k = kbeg + kk0 + 8 * r;
+    const bool in = k < kend;
     pa[r] = in ? pI[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
     pb[r] = in ? pJ[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -87,13 +99,13 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
     reinterpret_cast<float4 *>(&sb[kk0 + 8 * r][0])[c2] = pb[r];
   }
   __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += KB) {
-    const bool more = k0 + KB < K;
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
+    const bool more = k0 + KB < kend;
     if (more) {
 #pragma unroll
       for (int r = 0; r < kLoads; ++r) {
         const int k = k0 + KB + kk0 + 8 * r;
-        const bool in = k < K;
+        const bool in = k < kend;
         pa[r] = in ? pI[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
         pb[r] = in ? pJ[static_cast<size_t>(k) * rowf4] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
@@ -166,6 +178,15 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
 
   // epilogue: read-modify-write of the packed tile.  Accumulator register r of
   // lane l holds row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the quadrant.
+  if (piece > 0) {
+    float2 *Pt = P + (static_cast<size_t>(sidx) * parts + (piece - 1)) * (kTile * kTile);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      Pt[row * kTile + wj * 32 + li] = make_float2(accR[r], accI[r]);
+    }
+    return;
+  }
   const int nb = Npad / kTile;
   const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
   float2 *Ht = H + tile_index * (kTile * kTile);
@@ -184,6 +205,29 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
     if (I == J && row == col) h[r].y = 0.f;
     Ht[row * kTile + col] = h[r];
   }
+}
+
+// H(I, J) += sum over pieces p = 0..parts-1 of P[s][p], in increasing p, for
+// split tile s = blockIdx.x; 16 workgroups of 256 elements per tile.
+__global__ __launch_bounds__(256) void k_gram_fixup(int nb, int parts, const int2 *__restrict__ ij,
+                                                    const float2 *__restrict__ P,
+                                                    float2 *__restrict__ H) {
+  const int s = blockIdx.x;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  const float2 *q = P + static_cast<size_t>(s) * parts * (kTile * kTile) + e;
+  float2 acc = q[0];
+  for (int p = 1; p < parts; ++p) {
+    const float2 v = q[static_cast<size_t>(p) * (kTile * kTile)];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  const int I = ij[s].x, J = ij[s].y;
+  const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
+  float2 *h = H + tile_index * (kTile * kTile) + e;
+  float2 v = *h;
+  v.x += acc.x;
+  v.y += acc.y;
+  *h = v;
 }
 
 constexpr int kCorrPix = 32;    // pixels per workgroup
@@ -600,14 +644,31 @@ __global__ __launch_bounds__(256) void k_gram_entries(int n, int N, const float2
 
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
-  if (g.K > kMaxFreq) return hipErrorInvalidValue;
+                            const GramSplit &split, hipStream_t st, hipEvent_t t0,
+                            hipEvent_t t1) {
+  if (g.K > kMaxFreq || ntiles_grid % 8 != 0) return hipErrorInvalidValue;
+  const bool fix = split.nsplit > 0;
+  if (fix && (split.parts < 2 || split.parts > (g.K + kGramKB - 1) / kGramKB || !split.P || !split.ij))
+    return hipErrorInvalidValue;
+  // the events bracket both launches, so a timed Gram update includes the fix-up
   if (t0)
-    hipExtLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, t0, t1, 0,
-                          g.K, g.Npad, ntiles_grid, A, tile_ij, H, corr);
+    hipExtLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, t0,
+                          fix ? nullptr : t1, 0, g.K, g.Npad, ntiles_grid, A, tile_ij, H, corr,
+                          split.P, split.parts);
   else
     hipLaunchKernelGGL(k_gram_fp32<kGramKB>, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
-                       ntiles_grid, A, tile_ij, H, corr);
+                       ntiles_grid, A, tile_ij, H, corr, split.P, split.parts);
+  if (fix) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(split.nsplit, kTile * kTile / 256);
+    if (t0)
+      hipExtLaunchKernelGGL(k_gram_fixup, grid, dim3(256), 0, st, nullptr, t1, 0, g.Npad / kTile,
+                            split.parts, split.ij, static_cast<const float2 *>(split.P), H);
+    else
+      hipLaunchKernelGGL(k_gram_fixup, grid, dim3(256), 0, st, g.Npad / kTile, split.parts,
+                         split.ij, static_cast<const float2 *>(split.P), H);
+  }
   return hipGetLastError();
 }
 

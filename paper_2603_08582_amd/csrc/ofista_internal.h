@@ -159,9 +159,22 @@ struct CorrArgs {
   DevScalars *scal;
   int first;  // also record max |Delta b| (first pulse)
 };
+// Remainder split of the FP32 Gram update.  When the tile count is a few
+// rounds of one tile per CU plus a remainder, the last off-diagonal tiles are
+// split along the frequencies into `parts` pieces that run after the whole
+// tiles; each piece writes its 64 x 64 partial to P (tile-major, row-major
+// inside), and a second launch adds the pieces of each split tile in
+// increasing order and then adds that sum to H.  Table entries: x = I | split
+// index << 16, y = J | piece << 20 (piece 0: whole tile, 1..parts: part).
+struct GramSplit {
+  float2 *P;        // nsplit * parts partial tiles
+  const int2 *ij;   // (I, J) of each split tile
+  int nsplit, parts;
+};
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                            const GramSplit &split, hipStream_t st, hipEvent_t t0 = nullptr,
+                            hipEvent_t t1 = nullptr);
 hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
                                const int *ii, const int *jj, float2 *out, hipStream_t st);
 hipError_t launch_gram_dense(const Geom &g, const float2 *H,

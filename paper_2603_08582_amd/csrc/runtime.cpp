@@ -35,6 +35,9 @@ struct Layout {
   size_t bf_blocks = 0, nbf_blocks = 0;
   size_t atom_ptr = 0, atom_pix = 0, pix_ptr = 0, pix_atom = 0;
   size_t ntiles = 0, ntiles_grid = 0, nitems = 0;
+  // FP32 Gram remainder split: split tiles, pieces per tile, launch grid
+  size_t gsplit = 0, gram_grid = 0, gP = 0, gsplit_ij = 0;
+  int gparts = 0;
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
       sig2, gtoep, tile_ij, tile_row0, items, echo_tmp, Ahi, Alo;
@@ -120,6 +123,29 @@ long long coef_count(const ofista_config *c, size_t *nnz) {
 // this many tile rows on: measured faster at N = 16384 and 65536, slower at
 // N = 4096.
 constexpr int kBfBlockMinNb = 256;
+
+// FP32 Gram remainder split.  With q whole rounds of one tile per CU and a
+// remainder r, the r tiles of the last round run nearly alone on their CUs,
+// latency-bound: at N = 4096 (2080 tiles = 8 x 256 + 32) they cost 20 us of
+// 168.  Splitting r off-diagonal tiles into up to 8 frequency pieces that run
+// after the whole tiles shortens that tail (measured: 168 -> 158 us with the
+// pieces in a separate launch).  Beyond kSplitMaxRounds rounds the remainder
+// costs under 1% and the tiles are left whole; below 2 rounds every tile is
+// resident from the start and there is no tail of lone tiles.
+constexpr size_t kGramCUs = 256;  // compute units of the MI355X
+constexpr size_t kSplitMaxRounds = 64;
+constexpr int kSplitParts = 8;
+
+void plan_gram_split(Layout &L) {
+  L.gram_grid = L.ntiles_grid;
+  const size_t q = L.ntiles / kGramCUs, rem = L.ntiles % kGramCUs;
+  const int parts = std::min((L.K + kGramKB - 1) / kGramKB, kSplitParts);
+  if (q < 2 || q >= kSplitMaxRounds || rem == 0 || parts < 2 || rem > L.ntiles - L.nb) return;
+  L.gsplit = rem;
+  L.gparts = parts;
+  const size_t whole = L.ntiles - rem;  // q * kGramCUs, a multiple of 8
+  L.gram_grid = 8 * (whole / 8 + (rem * parts + 7) / 8);
+}
 
 // Run length of the FISTA work items.  Runs of 2 tiles measured faster than
 // runs of 4 or 8 at both N = 4096 and N = 16384 (more workgroups in flight).
@@ -222,6 +248,8 @@ Layout layout(const ofista_config *c) {
   L.store = c->storage == OFISTA_STORE_PULSES;
   L.ntiles = L.store ? 0 : static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
   L.ntiles_grid = (L.ntiles + 7) / 8 * 8;
+  L.gram_grid = L.ntiles_grid;
+  if (!L.store && c->precision == OFISTA_PREC_FP32) plan_gram_split(L);
   L.chunk = pick_chunk(L.nb);
   L.nparts = kUpdSplit * L.nb;
   L.nitems = count_items(L.nb, L.chunk);
@@ -257,7 +285,9 @@ Layout layout(const ofista_config *c) {
   L.pos = take(3 * static_cast<size_t>(L.npos) * sizeof(double));
   L.sig2 = take(L.npos * sizeof(double));
   L.gtoep = take(static_cast<size_t>(L.npos) * L.K * sizeof(double2));
-  L.tile_ij = take(L.ntiles_grid * sizeof(int2));
+  L.tile_ij = take(std::max(L.ntiles_grid, L.gram_grid) * sizeof(int2));
+  L.gP = take(L.gsplit * L.gparts * kTile * kTile * sizeof(float2));
+  L.gsplit_ij = take(L.gsplit * sizeof(int2));
   L.tile_row0 = take(L.nb * sizeof(int));
   L.items = take(L.nitems * sizeof(WorkItem));
   L.echo_tmp = take(L.K * sizeof(double2));
@@ -343,6 +373,8 @@ struct ofista_ctx {
   // store-all comparator buffers (NULL in the Gram mode)
   float2 *Gst = nullptr, *Dst = nullptr;
   const int2 *bf_blocks = nullptr;  // split-BF16 block table (large N), else NULL
+  float2 *gP = nullptr;              // FP32 Gram remainder pieces (else NULL)
+  const int2 *gsplit_ij = nullptr;   // (I, J) of the split tiles
   float4 *Ust = nullptr, *Pst = nullptr;
   DevState d{};
   hipStream_t st = nullptr;
@@ -547,7 +579,8 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
 
   // host tables
   const int nb = L.nb;
-  std::vector<int2> tij(L.ntiles_grid, make_int2(-1, -1));
+  std::vector<int2> tij(std::max(L.ntiles_grid, L.gram_grid), make_int2(-1, -1));
+  std::vector<int2> split_ij;
   std::vector<int> row0(nb);
   {
     // storage order: row-major upper tiles
@@ -565,6 +598,33 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
       for (int Qs = P; Qs < ns; ++Qs)
         for (int I = P * S; I < std::min(nb, P * S + S); ++I)
           for (int J = std::max(I, Qs * S); J < std::min(nb, Qs * S + S); ++J) tij[t++] = make_int2(I, J);
+    if (L.gsplit > 0) {
+      // The last gsplit off-diagonal tiles of that order are split.  XCD x
+      // (workgroups b = x mod 8) reads the table chunk [x per, (x+1) per):
+      // its eighth of the whole tiles, then the pieces k = x mod 8.
+      const std::vector<int2> ord(tij.begin(), tij.begin() + L.ntiles);
+      std::vector<char> cut(L.ntiles, 0);
+      for (size_t u = L.ntiles; u-- > 0 && split_ij.size() < L.gsplit;)
+        if (ord[u].x != ord[u].y) {
+          cut[u] = 1;
+          split_ij.push_back(ord[u]);
+        }
+      std::reverse(split_ij.begin(), split_ij.end());
+      std::vector<int2> whole, pieces;
+      for (size_t u = 0; u < L.ntiles; ++u)
+        if (!cut[u]) whole.push_back(ord[u]);
+      for (size_t sidx = 0; sidx < split_ij.size(); ++sidx)
+        for (int p = 1; p <= L.gparts; ++p)
+          pieces.push_back(make_int2(split_ij[sidx].x | static_cast<int>(sidx << 16),
+                                     split_ij[sidx].y | (p << 20)));
+      const size_t per = L.gram_grid / 8, wper = whole.size() / 8;
+      std::fill(tij.begin(), tij.end(), make_int2(-1, -1));
+      for (size_t x = 0; x < 8; ++x) {
+        size_t o = x * per;
+        for (size_t u = 0; u < wper; ++u) tij[o++] = whole[x * wper + u];
+        for (size_t k = x; k < pieces.size(); k += 8) tij[o++] = pieces[k];
+      }
+    }
   }
   std::vector<int2> bfb;
   if (L.nbf_blocks) {
@@ -577,6 +637,10 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
           for (int JB = std::max(IB, Qs * S); JB < std::min(nbB, Qs * S + S); ++JB)
             bfb.push_back(make_int2(IB, JB));
     c->bf_blocks = reinterpret_cast<const int2 *>(base + L.bf_blocks);
+  }
+  if (L.gsplit > 0) {
+    c->gP = reinterpret_cast<float2 *>(base + L.gP);
+    c->gsplit_ij = reinterpret_cast<const int2 *>(base + L.gsplit_ij);
   }
   // Full runs first, then the short last runs of the rows: the short items
   // then fill the tail of the pass instead of delaying full ones (-3% at
@@ -610,6 +674,10 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
     return fail(e, "copy block table");
   if ((e = hipMemcpyAsync(d.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy work items");
+  if (!split_ij.empty() &&
+      (e = hipMemcpyAsync(const_cast<int2 *>(c->gsplit_ij), split_ij.data(), split_ij.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->st)) != hipSuccess)
+    return fail(e, "copy split tiles");
   std::vector<int> aptr, apix, pptr, patom;
   if (edgelet) {
     edgelet_atoms(cfg, &aptr, &apix);
@@ -706,7 +774,8 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
     ProfScope p(c, kProfGram, true);
     CorrArgs corr{static_cast<const float2 *>(d_pulse), static_cast<float>(std::cos(phase_corr)),
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
-    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.ntiles_grid), corr,
+    const GramSplit split{c->gP, c->gsplit_ij, static_cast<int>(L.gsplit), L.gparts};
+    OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.gram_grid), corr, split,
                               c->st, p.t0(), p.t1()));
   }
   {

@@ -99,6 +99,12 @@ def test_echo():
     dict(),                                        # 32x32, K=64: 16 tile rows
     dict(n_side=30, patch_m=28.0, n_freq=50),      # ragged N (900) and K
     dict(n_side=8, patch_m=8.0, n_freq=16),        # a single tile
+    # 2304 and 2209 pixels (666 and 630 tiles: two rounds of one tile per CU
+    # and a remainder): the Gram update splits its last 154 / 118 tiles into
+    # frequency pieces and adds them in a second launch; K = 50 leaves a
+    # partial last stage inside the last piece
+    dict(n_side=48, patch_m=46.0, n_freq=64, n_pulses=4),
+    dict(n_side=47, patch_m=45.0, n_freq=50, n_pulses=4),
 ])
 def test_gram_b_and_scalars(shape):
     wl = make_workload(tiny_spec(**{**dict(n_side=32, patch_m=30.0, n_freq=64), **shape}))
