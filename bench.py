@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 from pathlib import Path
@@ -29,22 +30,27 @@ METRIC = "pulses/sec (Gram update + 20 FISTA iters) at 64×64 scene; % HBM/MFMA 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
-TRAFFIC_FILE = ROOT / "profiles" / "traffic_haar64.json"
-KERNEL_SOURCES = {"step": "paper_2603_08582_amd/csrc/fista.hip",
-                  "gram": "paper_2603_08582_amd/csrc/gram.hip"}
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the haar64 workload: a fenced
+# JSON block holds, per kernel class, the scaled HBM bytes per launch and a
+# hash of the sources those counters were taken on
+TRAFFIC_FILE = ROOT / "profiles" / "traffic-haar64.md"
 
 
-def source_hash(rel: str) -> str:
-    return hashlib.sha256((ROOT / rel).read_bytes()).hexdigest()[:16]
+def source_hash(files) -> str:
+    h = hashlib.sha256()
+    for rel in files:
+        h.update((ROOT / rel).read_bytes())
+    return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different kernel source."""
-    if not TRAFFIC_FILE.exists():
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    absent, for another workload, or taken on different kernel sources."""
+    if workload != "haar64" or not TRAFFIC_FILE.exists():
         return None
-    rec = json.loads(TRAFFIC_FILE.read_text()).get(kernel)
-    if not rec or rec.get("source_sha") != source_hash(KERNEL_SOURCES[kernel]):
+    m = re.search(r"```json\n(.*?)\n```", TRAFFIC_FILE.read_text(), re.S)
+    rec = json.loads(m.group(1)).get(kernel) if m else None
+    if not rec or rec.get("source_sha") != source_hash(rec.get("files", [])):
         return None
     return rec.get("bytes_per_launch")
 
@@ -229,10 +235,10 @@ def main():
     else:
         rl_gram = {"bound": "mfma", "achieved": gram_flops / (gram_avg * 1e-3) / 1e12,
                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "fp32",
-                   "traffic": traffic_for("gram"), "kernel": "k_gram_fp32", "avg_ms": gram_avg,
+                   "traffic": traffic_for("gram", args.workload), "kernel": "k_gram_fp32", "avg_ms": gram_avg,
                    "launches": gram_n}
     rl_step = {"bound": "hbm", "achieved": step_bytes / (step_avg * 1e-3) / 1e9,
-               "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step"),
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step", args.workload),
                "kernel": "k_step_tiles", "avg_ms": step_avg, "launches": step_n}
     for r in (rl_gram, rl_step):
         r["frac"] = r["achieved"] / r["peak"]

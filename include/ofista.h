@@ -42,6 +42,9 @@
 extern "C" {
 #endif
 
+/* Opaque context of one reconstruction (host memory owned by the library). */
+struct ofista_ctx;
+
 typedef enum ofista_status {
   OFISTA_OK = 0,
   OFISTA_E_ARG = -1,         /* null pointer, bad size or enum value         */

@@ -4,7 +4,9 @@
 
 Every HIP source is compiled with packed-FP32 instructions disabled
 (-target-feature -packed-fp32-ops) and linked into one shared library next
-to this file.  The oracle's C parts (if any) are built by __graft_entry__.
+to this file.  The test suite's plain-C driver of the ABI (tests/c) is built
+against it with the host C compiler.  The oracle's C parts (if any) are built
+by __graft_entry__.
 """
 
 from __future__ import annotations
@@ -57,6 +59,27 @@ def _compile(src: str) -> Path:
     return obj
 
 
+ROCM = Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
+CDRIVER = HERE.parent / "tests" / "c" / "ofista_run.c"
+
+
+def build_c_driver(lib: Path = LIB) -> Path:
+    """Compile tests/c/ofista_run.c (C11, HIP runtime C API) against lib."""
+    cc = os.environ.get("CC") or shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the ABI driver")
+    exe = CDRIVER.with_suffix("")
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           f"-I{ROCM / 'include'}", f"-I{INCLUDE}", str(CDRIVER), "-o", str(exe),
+           f"-L{lib.parent}", "-lofista", f"-L{ROCM / 'lib'}", "-lamdhip64", "-lm",
+           f"-Wl,-rpath,$ORIGIN/{os.path.relpath(lib.parent, exe.parent)}",
+           f"-Wl,-rpath,{ROCM / 'lib'}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C driver build failed:\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 def build(verbose: bool = False) -> Path:
     with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -67,8 +90,10 @@ def build(verbose: bool = False) -> Path:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    exe = build_c_driver(LIB)
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
+        print(f"built {exe}", file=sys.stderr)
     return LIB
 
 
