@@ -269,7 +269,9 @@ ofista_status ofista_set_lambda(struct ofista_ctx *ctx, double lambda);
    launch of the named kernel class is bracketed by a pair of events.
    ofista_kernel_time synchronises and returns the summed milliseconds and the
    launch count since enabling.  kernel: 0 Gram update (with the correlation
-   b += A_s^H d fused in), 1 FISTA-step tile pass (the H z / H w streaming),
+   b += A_s^H d fused in; when the library splits the last tiles into
+   frequency pieces, the pair of events spans the Gram launch and the launch
+   that adds the pieces to H), 1 FISTA-step tile pass (the H z / H w streaming),
    2 rows, 3 correlation (separate launch on the split-BF16 path only),
    4 scalars, 5 FISTA-step update (slot sums, shrink, momentum, power
    vector), 6 and 7 the two passes over the stored pulses of the PULSES
