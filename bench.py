@@ -55,9 +55,11 @@ def traffic_for(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, pulses: int, positions=None):
+def cpu_baseline(wl, pulses: int, positions=None, diff: bool = False):
     """The FP64 oracle as it stands, on the first `pulses` pulses (of
-    `positions` when given: the Bernoulli-selected ones of a session)."""
+    `positions` when given: the Bernoulli-selected ones of a session).  With
+    diff, the oracle's forward run plus its reverse pass for dL/dlambda and
+    dL/dphase over those pulses (the differentiation form's step)."""
     from oracle import sar
     from oracle.online_fista import OnlineFistaOracle
     try:
@@ -71,6 +73,18 @@ def cpu_baseline(wl, pulses: int, positions=None):
     d = sar.echoes(wl, pulses=order)
     o = OnlineFistaOracle.from_workload(wl)
     m = wl.spec.inner_steps
+    if diff:
+        from oracle import adjoint
+        o.push_pulse(d[0], 0)
+        lam = o.lam
+        t0 = time.perf_counter()
+        adjoint.gradients(wl, d, lam, np.zeros(len(order)), m, np.abs(wl.rho), pulses=len(order))
+        dt = time.perf_counter() - t0
+        return {"value": len(order) / dt, "unit": "pulses/s", "cores": int(threads),
+                "kind": "oracle",
+                "sample": f"first {len(order)} of the {len(order_all)} pulses of the same workload: "
+                          f"recorded forward ({m} FISTA steps per pulse) and the reverse pass for "
+                          f"dL/dlambda and dL/dphase, numpy complex128, {dt:.1f} s"}
     t0 = time.perf_counter()
     for p in order:
         o.push_pulse(d[p], p)
@@ -294,7 +308,8 @@ def main():
                     "gradient (loss_ms) + reverse pass for dL/dlambda and dL/dphase with "
                     "L = sum(|x| - |rho|)^2 (backward_ms)"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pulses, sched if session_mode else None)
+        out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_pulses, 8) if diff_mode else args.cpu_pulses,
+                                           sched if session_mode else None, diff=diff_mode)
     print(json.dumps(out), flush=True)
 
 
