@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="haar64")
     ap.add_argument("--cpu-pulses", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="BLAS threads of the oracle baseline (0: the library's default, all cores)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -308,8 +310,14 @@ def main():
                     "gradient (loss_ms) + reverse pass for dL/dlambda and dL/dphase with "
                     "L = sum(|x| - |rho|)^2 (backward_ms)"}
     if not args.no_cpu_baseline:
+        limit = None
+        if args.cpu_threads > 0:
+            from threadpoolctl import threadpool_limits
+            limit = threadpool_limits(limits=args.cpu_threads, user_api="blas")
         out["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_pulses, 8) if diff_mode else args.cpu_pulses,
                                            sched if session_mode else None, diff=diff_mode)
+        if limit is not None:
+            limit.restore_original_limits()
     print(json.dumps(out), flush=True)
 
 
