@@ -10,6 +10,9 @@
  *                           pushed pulses of seeded pseudo-random data: a
  *                           fixed, self-contained launch sequence for counter
  *                           collection
+ *   ofista_run --xlarge P   the 256 x 256 identity workload shape (K = 1024,
+ *                           512 positions over 40 degrees, m = 10, split-BF16
+ *                           Gram update) with P pushed pulses of seeded data
  *   ofista_run --copy MIB   one device-to-device copy of MIB MiB (the known
  *                           byte count that scales the memory counters)
  *
@@ -82,32 +85,35 @@ static int load(const char *path, problem *pb) {
   return ok;
 }
 
-/* The 64 x 64 Haar workload shape, with pulse data from a 64-bit LCG. */
-static void haar64(problem *pb, int32_t n_push) {
+/* A square identity or Haar workload shape on the 10 km / 1 km circle, with
+   pulse data from a 64-bit LCG. */
+static void synthetic(problem *pb, int32_t n_push, int n, int P, int K, double patch,
+                      double arc_deg, double f_lo, double f_hi, int dict, int levels,
+                      int precision, int iters) {
   ofista_config *c = &pb->cfg;
   memset(pb, 0, sizeof *pb);
-  const int n = 64, P = 128, K = 256;
-  const double patch = 60.0, dxy = patch / n, pi = 3.14159265358979323846;
+  const double dxy = patch / n, pi = 3.14159265358979323846;
   c->n_x = c->n_y = n;
   c->x0 = c->y0 = -patch / 2 + dxy / 2;
   c->dx = c->dy = dxy;
   c->n_pos = P;
   pb->pos = malloc(sizeof(double) * 3 * P);
   for (int s = 0; s < P; ++s) {
-    const double th = s * (20.0 * pi / 180.0) / (P - 1);
+    const double th = s * (arc_deg * pi / 180.0) / (P - 1);
     pb->pos[3 * s] = 10000.0 * cos(th);
     pb->pos[3 * s + 1] = 10000.0 * sin(th);
     pb->pos[3 * s + 2] = 1000.0;
   }
   c->pos_xyz = pb->pos;
   c->n_freq = K;
-  c->freq0_hz = 9.8e9;
-  c->dfreq_hz = 0.4e9 / (K - 1);
-  c->dict = OFISTA_DICT_HAAR2D;
-  c->haar_levels = 3;
+  c->freq0_hz = f_lo;
+  c->dfreq_hz = (f_hi - f_lo) / (K - 1);
+  c->dict = dict;
+  c->haar_levels = levels;
+  c->precision = precision;
   c->lambda = 0.05;
   c->lambda_relative = 1;
-  pb->iters = 20;
+  pb->iters = iters;
   pb->n_push = n_push;
   pb->order = malloc(sizeof(int32_t) * (size_t)(n_push + 1));
   pb->pulses = malloc(sizeof(float) * 2 * (size_t)K * (size_t)(n_push + 1));
@@ -146,7 +152,13 @@ int main(int argc, char **argv) {
   if (argc == 3 && strcmp(argv[1], "--haar64") == 0) {
     const int n = atoi(argv[2]);
     if (n < 1) return 1;
-    haar64(&pb, n);
+    synthetic(&pb, n, 64, 128, 256, 60.0, 20.0, 9.8e9, 10.2e9, OFISTA_DICT_HAAR2D, 3,
+              OFISTA_PREC_FP32, 20);
+  } else if (argc == 3 && strcmp(argv[1], "--xlarge") == 0) {
+    const int n = atoi(argv[2]);
+    if (n < 1) return 1;
+    synthetic(&pb, n, 256, 512, 1024, 250.0, 40.0, 9.7e9, 10.3e9, OFISTA_DICT_IDENTITY, 0,
+              OFISTA_PREC_SPLIT_BF16, 10);
   } else if (argc == 3) {
     if (!load(argv[1], &pb)) {
       fprintf(stderr, "cannot read %s\n", argv[1]);
@@ -154,7 +166,7 @@ int main(int argc, char **argv) {
     }
     out = argv[2];
   } else {
-    fprintf(stderr, "usage: ofista_run FILE OUT | ofista_run --haar64 PULSES | ofista_run --copy MIB\n");
+    fprintf(stderr, "usage: ofista_run FILE OUT | ofista_run --haar64 PULSES | ofista_run --xlarge PULSES | ofista_run --copy MIB\n");
     return 1;
   }
   ofista_config *c = &pb.cfg;
