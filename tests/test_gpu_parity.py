@@ -105,6 +105,9 @@ def test_echo():
     # partial last stage inside the last piece
     dict(n_side=48, patch_m=46.0, n_freq=64, n_pulses=4),
     dict(n_side=47, patch_m=45.0, n_freq=50, n_pulses=4),
+    # 2025 pixels, K = 21 (odd: the last frequency pair of the three-product
+    # form is half padding): 528 tiles, the last 16 split into 2 pieces
+    dict(n_side=45, patch_m=44.0, n_freq=21, n_pulses=3),
 ])
 def test_gram_b_and_scalars(shape):
     wl = make_workload(tiny_spec(**{**dict(n_side=32, patch_m=30.0, n_freq=64), **shape}))
