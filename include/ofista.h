@@ -144,7 +144,8 @@ typedef struct ofista_stats {
 
 /* Device bytes the workspace must have for cfg (H, b, coefficient and momentum
    vectors, power vector, matvec partials, one pulse's A_s, tables, the partial
-   tiles of the FP32 Gram update's split remainder (up to 8 MB), and the
+   tiles of the FP32 Gram update's split remainder (at most 255 x 8 tiles of
+   32 KB, 8 MB at N = 4096), and the
    recording buffers when record_every > 0).  Pure host function, needs no GPU.
    Returns 0 when cfg is invalid. */
 size_t ofista_workspace_bytes(const ofista_config *cfg);
