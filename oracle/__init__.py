@@ -26,11 +26,13 @@ trajectory of Algorithm 1 at m inner steps is "parity unpinned" as a whole:
 no closed form exists for it, so its parts are pinned separately (Hermitian
 PSD Gram, batch identity, closed-form single-scatterer fixed point, KKT
 certificate, brute-force batch LASSO after continuation, ISTA-mode descent,
-scatterers landing on their pixels, phase equivariance, Lipschitz upper bound).
+scatterers landing on their pixels, phase equivariance, Lipschitz upper bound,
+closed-form spectral norms, momentum carried across pulses, warm start, and
+the sign of the autofocus phase correction).
 """
 
 from . import dictionary, lasso, memory, sar
-from .online_fista import OnlineFistaOracle, soft_threshold, power_sigma2
+from .online_fista import OnlineFistaOracle, soft_threshold, spectral_norm_sq
 
 __all__ = ["dictionary", "lasso", "memory", "sar", "OnlineFistaOracle",
-           "soft_threshold", "power_sigma2"]
+           "soft_threshold", "spectral_norm_sq"]

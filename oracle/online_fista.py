@@ -1,35 +1,40 @@
 """Online FISTA in FP64, step by step (test infrastructure).
 
-Follows Section III-C of the paper and its Algorithm 1 ("Online FISTA per
-pulse"), with R_n = I (white noise; the noise power is absorbed into lambda):
+Follows Section III-C of the paper and its Algorithm 1 (Online FISTA per
+pulse), with R_n = I (white noise; the noise power is absorbed into lambda).
 
-push_pulse(d_s, s)                       -- one received pulse
-    A_s   = F_s W                          (Section III-A, eq. for G)
-    d~    = d_s * exp(-i phase_corr)       (autofocus correction; 0 by default)
-    H    += A_s^H A_s,  b += A_s^H d~      (Delta-A / Delta-b and A_n / b_n eqs.)
-    lambda = lambda_rel * max_i |A_1^H d~_1|   at the first pulse only
-    L_n   from one of three rules, tau = 1 / L_n:
-        "running": rho_{n-1} + sigma_n^2   (rho = Rayleigh quotient of the running
-                   power vector w on H; sigma_n^2 = ||A_s||_2^2).  This is the
-                   paper's incremental bound L_{n+1} <= L_n + ||G_n||^2 with the
-                   previous bound replaced by the running spectral estimate of
-                   the Section III-B condition L >= ||sum G^H G||_2.
-        "bound":   L_{n-1} + sigma_n^2     (the incremental bound taken literally)
-        "exact":   lambda_max(H_n)         (tests only)
+One received pulse (``push_pulse``):
+  * the per-pulse operator A_s = F_s W (Section III-A, eq. for G) and the data
+    rotated by the autofocus correction, d~ = d_s exp(-i phase_corr);
+  * the sufficient statistics grow by A_s^H A_s and A_s^H d~ (the Delta-A /
+    Delta-b and A_n / b_n equations);
+  * lambda = lambda_rel * max_i |A_1^H d~_1| at the first pulse only;
+  * the step 1/L_n.  Section III-B asks for L >= ||sum G^H G||_2 and Section
+    III-C bounds its growth by ||G_n||_2^2 per pulse.  sigma_n^2 = ||A_s||_2^2
+    is the largest eigenvalue of the K x K matrix A_s A_s^H (its definition;
+    a library eigen-solver is the step).  Three rules:
+      "running": rho + (sum of sigma^2 of the pulses pushed since the last
+                 FISTA step).  rho is the Rayleigh quotient of a power vector
+                 advanced once per FISTA step on the H of that step (0 before
+                 any step).  This is the incremental bound with the previous
+                 bound replaced by the running spectral estimate; summing over
+                 every pulse pushed since that estimate keeps it a Weyl bound
+                 when several pulses arrive between reconstructions.
+      "bound":   L_{n-1} + sigma_n^2 (the incremental bound taken literally).
+      "exact":   lambda_max(H_n) (tests only); "given": replayed values.
 
-reconstruct(iters)                       -- Algorithm 1, iters inner steps
-    c0 = c_hat_{n-1}, z = c0, t = t_{n-1} (t = 1 at the first pulse)
-    repeat: g = H z - b; u = z - tau g; c = S_{lambda tau}(u);
-            t' = (1 + sqrt(1 + 4 t^2)) / 2;  z = c + ((t - 1) / t') (c - c_prev)
-    every step also advances the power vector: y = H w, rho = Re(w^H y), w = y/|y|
-    return c_hat_n = c, t_n = t'
+Reconstruction (``reconstruct``, Algorithm 1 with `iters` inner steps) is a
+proximal-gradient (forward-backward) iteration on J_n with Nesterov-type
+extrapolation, warm-started at c_hat_{n-1}:
+  * step: c = S_{lambda tau}(z - tau (H z - b)) (``prox_gradient``);
+  * extrapolation weights from the momentum scalar carried across pulses
+    (``momentum_schedule``); the extrapolated point starts at c_hat_{n-1};
+  * the power vector advances once per step on the same H.
 
 Readings of garbled or silent points: the shrink threshold is lambda*tau (the
 printed subscript uses the momentum t), the shrink is the complex proximal map
 u * max(0, 1 - alpha/|u|) (the printed formula drops the phase), coefficients
-are complex, sigma_n^2 comes from an FP64 power iteration on the K x K matrix
-A_s A_s^H started at 1/sqrt(K), stopped when the Rayleigh quotient moves by at
-most 1e-13 relative or after 200 steps; w starts at 1/sqrt(M) and rho_0 = 0.
+are complex, the power vector starts at 1/sqrt(M).
 
 Test-only switches: momentum "restart" (t = 1 every pulse) and "ista"
 (no momentum), the "exact" and "given" Lipschitz rules, and kernel sign +1.
@@ -47,9 +52,6 @@ import numpy as np
 from . import sar
 from .dictionary import synthesis_matrix
 
-POWER_MAX_STEPS = 200
-POWER_REL_TOL = 1e-13
-
 
 def soft_threshold(u: np.ndarray, alpha: float) -> np.ndarray:
     """Complex soft threshold S_alpha(u)_i = u_i max(0, 1 - alpha/|u_i|); 0 when
@@ -61,31 +63,36 @@ def soft_threshold(u: np.ndarray, alpha: float) -> np.ndarray:
     return out
 
 
-def power_sigma2(M: np.ndarray) -> float:
-    """lambda_max of a Hermitian PSD matrix by power iteration (FP64).
-
-    v_0 = 1/sqrt(K); each step y = M v, q = Re(v^H y), v = y/|y|; stop when
-    |q - q_prev| <= 1e-13 |q| or after 200 steps; returns the last q.
-    """
-    K = M.shape[0]
-    v = np.full(K, 1.0 / math.sqrt(K), dtype=np.complex128)
-    q_prev = None
-    q = 0.0
-    for _ in range(POWER_MAX_STEPS):
-        y = M @ v
-        q = float(np.vdot(v, y).real)
-        if q_prev is not None and abs(q - q_prev) <= POWER_REL_TOL * abs(q):
-            break
-        q_prev = q
-        nrm = float(np.linalg.norm(y))
-        if nrm == 0.0:
-            break
-        v = y / nrm
-    return q
+def spectral_norm_sq(A: np.ndarray) -> float:
+    """||A||_2^2 = largest eigenvalue of the Hermitian PSD matrix A A^H (FP64)."""
+    return float(np.linalg.eigvalsh(A @ A.conj().T)[-1])
 
 
 def t_next(t: float) -> float:
+    """Momentum scalar of the next step, the positive root of t'^2 - t' = t^2."""
     return (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+
+
+def momentum_schedule(t0: float, iters: int, mode: str = "fista"):
+    """Extrapolation weights beta_1..beta_iters of one reconstruction and the
+    momentum scalar after it.  beta_k = (t_k - 1)/t_{k+1}, t_1 = t0; "ista"
+    keeps beta = 0 (the scalar still advances, as it does not feed back)."""
+    betas = []
+    t = t0
+    for _ in range(iters):
+        tn = t_next(t)
+        betas.append(0.0 if mode == "ista" else (t - 1.0) / tn)
+        t = tn
+    return betas, t
+
+
+def prox_gradient(H: np.ndarray, b: np.ndarray, z: np.ndarray, tau: float,
+                  alpha: float):
+    """Forward-backward step on J(c) = 1/2 c^H H c - Re(b^H c) + lambda |c|_1:
+    gradient step of length tau on the smooth part, then the l1 prox with
+    threshold alpha = lambda tau.  Returns (u, c) with u the gradient point."""
+    u = z - tau * (H @ z - b)
+    return u, soft_threshold(u, alpha)
 
 
 class OnlineFistaOracle:
@@ -136,7 +143,8 @@ class OnlineFistaOracle:
         self.tau = 0.0
         self.lam = 0.0 if self.lam_abs is None else float(self.lam_abs)
         self.w = np.full(M, 1.0 / math.sqrt(M), dtype=np.complex128)
-        self.rho_hat = 0.0
+        self.rho_hat = 0.0      # Rayleigh quotient of w at the last FISTA step
+        self.sigma2_acc = 0.0   # sum of sigma^2 pushed since that step
         self.n = 0
         self.history = []
 
@@ -149,54 +157,54 @@ class OnlineFistaOracle:
     def push_pulse(self, d: np.ndarray, s: int, phase_corr: float = 0.0):
         A = self.rows(s)
         dt = np.asarray(d, np.complex128) * np.exp(-1j * phase_corr)
-        dH = A.conj().T @ A
         db = A.conj().T @ dt
-        self.H += dH
+        self.H += A.conj().T @ A
         self.b += db
         self.n += 1
         if self.n == 1 and self.lam_abs is None:
             self.lam = self.lam_rel * float(np.max(np.abs(db)))
-        sigma2 = power_sigma2(A @ A.conj().T)
+        self.sigma2 = spectral_norm_sq(A)
+        self.sigma2_acc += self.sigma2
         if self.lip == "running":
-            L = self.rho_hat + sigma2
+            L = self.rho_hat + self.sigma2_acc
         elif self.lip == "bound":
-            L = self.L + sigma2
+            L = self.L + self.sigma2
         elif self.lip == "exact":
             L = float(np.linalg.eigvalsh(self.H)[-1])
         elif self.lip == "given":
             L = float(self.given_L[self.n - 1])
         else:
             raise ValueError(self.lip)
-        self.sigma2 = sigma2
         self.L = L
         self.tau = 1.0 / L
+
+    def _power_step(self):
+        """One power-iteration step of the running spectral estimate on H."""
+        y = self.H @ self.w
+        self.rho_hat = float(np.vdot(self.w, y).real)
+        self.w = y / np.linalg.norm(y)
+        self.sigma2_acc = 0.0
 
     def reconstruct(self, iters: int, trace=None) -> np.ndarray:
         """Algorithm 1 with `iters` inner steps on the current (H_n, b_n)."""
         if self.n == 0:
             raise RuntimeError("reconstruct before any pulse")
-        H, b, tau = self.H, self.b, self.tau
+        tau = self.tau
         alpha = self.lam * tau
-        c_prev = self.c.copy()
-        z = c_prev.copy()
-        t = 1.0 if (self.n == 1 or self.momentum == "restart") else self.t
+        first = self.n == 1 or self.momentum == "restart"
+        betas, t_end = momentum_schedule(1.0 if first else self.t, iters, self.momentum)
+        c_prev = self.c.copy()   # c_hat_{n-1}
+        z = c_prev               # warm start of the extrapolated point
         c = c_prev
-        for _ in range(iters):
-            yw = H @ self.w
-            self.rho_hat = float(np.vdot(self.w, yw).real)
-            self.w = yw / np.linalg.norm(yw)
-            g = H @ z - b
-            u = z - tau * g
-            c = soft_threshold(u, alpha)
-            tn = t_next(t)
-            beta = 0.0 if self.momentum == "ista" else (t - 1.0) / tn
+        for beta in betas:
+            self._power_step()
+            u, c = prox_gradient(self.H, self.b, z, tau, alpha)
             if trace is not None:
                 trace.append(dict(z=z, u=u, c=c, beta=beta))
             z = c + beta * (c - c_prev)
             c_prev = c
-            t = tn
         self.c = c
-        self.t = t
+        self.t = t_end
         self.history.append(dict(n=self.n, L=self.L, tau=self.tau, t=self.t,
                                  rho_hat=self.rho_hat, lam=self.lam))
         return c

@@ -28,7 +28,7 @@ import numpy as np
 
 from . import sar
 from .dictionary import synthesis_matrix
-from .online_fista import power_sigma2, soft_threshold, t_next
+from .online_fista import momentum_schedule, soft_threshold, spectral_norm_sq
 
 
 class StoreAllFistaOracle:
@@ -47,7 +47,7 @@ class StoreAllFistaOracle:
         self.G, self.d = [], []
         self.c = np.zeros(self.M, np.complex128)
         self.w = np.full(self.M, 1.0 / math.sqrt(self.M), np.complex128)
-        self.t, self.rho_hat, self.n = 1.0, 0.0, 0
+        self.t, self.rho_hat, self.sigma2_acc, self.n = 1.0, 0.0, 0.0, 0
         self.lam = 0.0 if lam is None else float(lam)
 
     @classmethod
@@ -78,26 +78,26 @@ class StoreAllFistaOracle:
         self.n += 1
         if self.n == 1 and self.lam_abs is None:
             self.lam = self.lam_rel * float(np.max(np.abs(G.conj().T @ dt)))
-        self.sigma2 = power_sigma2(G @ G.conj().T)
-        self.L = self.rho_hat + self.sigma2
+        self.sigma2 = spectral_norm_sq(G)
+        self.sigma2_acc += self.sigma2
+        self.L = self.rho_hat + self.sigma2_acc
         self.tau = 1.0 / self.L
 
     def reconstruct(self, iters: int):
         tau, alpha = self.tau, self.lam * self.tau
+        betas, t_end = momentum_schedule(1.0 if self.n == 1 else self.t, iters)
         c_prev = self.c.copy()
-        z = c_prev.copy()
-        t = 1.0 if self.n == 1 else self.t
+        z = c_prev
         c = c_prev
-        for _ in range(iters):
+        for beta in betas:
             yw = self._normal(self.w, False)
             self.rho_hat = float(np.vdot(self.w, yw).real)
             self.w = yw / np.linalg.norm(yw)
-            g = self._normal(z, True)
-            c = soft_threshold(z - tau * g, alpha)
-            tn = t_next(t)
-            z = c + ((t - 1.0) / tn) * (c - c_prev)
-            c_prev, t = c, tn
-        self.c, self.t = c, t
+            self.sigma2_acc = 0.0
+            c = soft_threshold(z - tau * self._normal(z, True), alpha)
+            z = c + beta * (c - c_prev)
+            c_prev = c
+        self.c, self.t = c, t_end
         return c
 
     def stored_values(self) -> int:

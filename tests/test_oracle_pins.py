@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import dictionary, lasso, memory, sar
-from oracle.online_fista import OnlineFistaOracle, power_sigma2, soft_threshold, t_next
+from oracle.online_fista import OnlineFistaOracle, soft_threshold, spectral_norm_sq, t_next
 from workload import make_workload, spec
 
 
@@ -202,43 +202,212 @@ def test_momentum_sequence_bounds():
 
 
 # ---------------------------------------------------------------- Lipschitz
-def test_power_iteration_converges_on_separated_spectrum():
-    rng = np.random.default_rng(2)
-    Q, _ = np.linalg.qr(rng.normal(size=(12, 12)) + 1j * rng.normal(size=(12, 12)))
-    lam = np.array([10.0, 3, 2, 1, 1, 0.5, 0.2, 0.1, 0, 0, 0, 0])
-    M = (Q * lam) @ Q.conj().T
-    assert abs(power_sigma2(M) - 10.0) < 1e-10
+C0 = 299_792_458.0
 
 
-def test_power_iteration_never_exceeds_lambda_max():
-    wl = make_workload("small")
-    F = sar.forward_rows(wl.positions[0], wl.pixel_xyz(), wl.freqs())
-    M = F @ F.conj().T
-    q = power_sigma2(M)
-    top = np.linalg.eigvalsh(M)[-1]
-    assert q <= top * (1 + 1e-12)
-    assert q >= top * (1 - 1e-2)
+def _ring(n_pix, radius, h=1000.0, phase0=0.3):
+    """n_pix pixels on the z = 0 circle of the given radius around the nadir
+    of a platform at (0, 0, h): all of them at the same range."""
+    a = phase0 + 2 * math.pi * np.arange(n_pix) / n_pix
+    return np.stack([radius * np.cos(a), radius * np.sin(a), np.zeros(n_pix)], axis=1)
+
+
+def test_spectral_norm_equal_ranges_closed_form():
+    """Every pixel at one range makes every column of F_s the same unit-modulus
+    vector u (|u|^2 = K): F_s F_s^H = N u u^H, so ||F_s||_2^2 = N K exactly,
+    while the largest diagonal entry is only N."""
+    pos = np.array([0.0, 0.0, 1000.0])
+    pix = _ring(7, 35.0)
+    f = 9.9e9 + 3.1e6 * np.arange(5)
+    A = sar.forward_rows(pos, pix, f)
+    assert math.isclose(spectral_norm_sq(A), 7 * 5, rel_tol=1e-12)
+
+
+def test_spectral_norm_two_ranges_closed_form():
+    """Two groups of n1 and n2 pixels at ranges R1, R2: F_s F_s^H =
+    n1 a a^H + n2 b b^H with |a|^2 = |b|^2 = K, whose top eigenvalue is that of
+    the 2 x 2 Gram of (sqrt(n1) a, sqrt(n2) b):
+    (K(n1+n2) + sqrt(K^2 (n1-n2)^2 + 4 n1 n2 |a^H b|^2)) / 2, with a^H b the
+    geometric sum  sum_k q^k e^{i w0 dR},  q = e^{i dw dR}."""
+    pos = np.array([0.0, 0.0, 1000.0])
+    n1, n2 = 5, 3
+    pix = np.concatenate([_ring(n1, 20.0), _ring(n2, 40.0, phase0=1.1)])
+    f0, df, K = 9.8e9, 1.5e6, 64
+    f = f0 + df * np.arange(K)
+    R1 = math.hypot(20.0, 1000.0)
+    R2 = math.hypot(40.0, 1000.0)
+    w0, dw = 4 * math.pi * f0 / C0, 4 * math.pi * df / C0
+    q = np.exp(1j * dw * (R1 - R2))
+    ab = np.exp(1j * w0 * (R1 - R2)) * (1 - q ** K) / (1 - q)
+    expect = (K * (n1 + n2) + math.sqrt(K * K * (n1 - n2) ** 2 + 4 * n1 * n2 * abs(ab) ** 2)) / 2
+    A = sar.forward_rows(pos, pix, f)
+    got = spectral_norm_sq(A)
+    assert math.isclose(got, expect, rel_tol=1e-9)
+    # a partly coherent pair: neither the rank-one value nor the larger group alone
+    assert K * max(n1, n2) * (1 + 1e-2) < got < K * (n1 + n2) * (1 - 1e-2)
+
+
+@pytest.mark.parametrize("name", ["small", "haar64"])
+def test_spectral_norm_two_frequencies_closed_form(name):
+    """K = 2 on a workload's own geometry: F_s F_s^H = [[N, g], [conj g, N]] with
+    g = sum_i exp(-i 4 pi (f_0 - f_1) R_i / c0), so ||F_s||_2^2 = N + |g|."""
+    wl = make_workload(name)
+    pix = wl.pixel_xyz()
+    f = wl.freqs()[:2]
+    for s in (0, wl.spec.n_pulses - 1):
+        R = np.sqrt(np.sum((pix - wl.positions[s]) ** 2, axis=1))
+        g = np.sum(np.exp(1j * 4 * math.pi * (f[1] - f[0]) * R / C0))
+        expect = wl.n_pixels + abs(g)
+        assert math.isclose(spectral_norm_sq(sar.forward_rows(wl.positions[s], pix, f)),
+                            expect, rel_tol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["small", "haar64"])
+def test_spectral_norm_between_rayleigh_and_trace(name):
+    """On the full workload rows: every Rayleigh quotient |A^H v|^2 of a unit
+    vector is below ||A||_2^2, the trace KN above it."""
+    wl = make_workload(name)
+    A = sar.forward_rows(wl.positions[1], wl.pixel_xyz(), wl.freqs())
+    top = spectral_norm_sq(A)
+    rng = np.random.default_rng(5)
+    K, N = A.shape
+    for _ in range(5):
+        v = rng.normal(size=K) + 1j * rng.normal(size=K)
+        v /= np.linalg.norm(v)
+        assert np.linalg.norm(A.conj().T @ v) ** 2 <= top * (1 + 1e-12)
+    assert top <= K * N * (1 + 1e-12)
 
 
 @pytest.mark.parametrize("lip", ["running", "bound"])
-def test_step_rule_is_an_upper_bound(lip):
-    """Section III-B condition L >= ||sum G^H G||_2, checked at every pulse.
-
-    At the first pulse L_1 = sigma_1^2 is a Rayleigh quotient of a 200-step
-    power iteration, hence never above lambda_max(H_1) and (on these clustered
-    spectra) a little below it; from the second pulse on, the Weyl slack of
-    both rules keeps L_n above lambda_max(H_n)."""
-    wl = tiny(n_pulses=10)
+@pytest.mark.parametrize("dict_kind", ["identity", "haar"])
+def test_step_rule_is_an_upper_bound(lip, dict_kind):
+    """Section III-B condition L >= ||sum G^H G||_2 at every pulse, the first
+    one included (there L_1 = ||A_s||_2^2 = lambda_max(H_1))."""
+    wl = tiny(n_pulses=10, dictionary=dict_kind, haar_levels=2 if dict_kind == "haar" else 0)
     d = sar.echoes(wl)
     o = OnlineFistaOracle.from_workload(wl, lip=lip)
     for p in range(wl.spec.n_pulses):
         o.push_pulse(d[p], p)
         top = np.linalg.eigvalsh(o.H)[-1]
+        assert o.L >= top * (1 - 1e-9)
         if p == 0:
-            assert top * (1 - 1e-3) <= o.L <= top * (1 + 1e-12)
-        else:
-            assert o.L >= top * (1 - 1e-9)
+            assert math.isclose(o.L, top, rel_tol=1e-9)
         o.reconstruct(20)
+
+
+@pytest.mark.parametrize("pattern", ["all_then_reconstruct", "reconstruct_zero_between"])
+def test_step_rule_with_several_pulses_between_steps(pattern):
+    """Pulses pushed with no FISTA step between them still add their
+    ||G_n||_2^2 to the bound (Section III-C increments), so L stays above
+    lambda_max(H_n) and the iteration stays bounded."""
+    wl = tiny(n_pulses=8)
+    d = sar.echoes(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    if pattern == "all_then_reconstruct":
+        schedule = [0] * 7 + [40]
+    else:
+        schedule = [20, 0, 0, 20, 0, 0, 0, 20]
+    for p, iters in enumerate(schedule):
+        o.push_pulse(d[p], p)
+        assert o.L >= np.linalg.eigvalsh(o.H)[-1] * (1 - 1e-9)
+        o.reconstruct(iters)
+    assert np.all(np.isfinite(o.c))
+    assert np.abs(o.c).max() < 10 * np.abs(wl.rho).max()
+
+
+# ---------------------------------------------------------------- momentum and warm start
+def test_momentum_is_carried_across_pulses():
+    """Algorithm 1 starts each pulse from t_{n-1}.  From t' = (1 + sqrt(1 + 4t^2))/2
+    follow t + 1/2 <= t' <= t + 1, so after n pulses of m steps from t = 1 the
+    carried scalar lies in [1 + nm/2, 1 + nm]; restarting every pulse would keep
+    it in [1 + m/2, 1 + m].  Exact start: one step from t = 1 gives the golden
+    ratio, the root of t^2 = t + 1."""
+    wl = tiny(n_pulses=6)
+    d = sar.echoes(wl)
+    m = 7
+    o = OnlineFistaOracle.from_workload(wl)
+    r = OnlineFistaOracle.from_workload(wl, momentum="restart")
+    for p in range(wl.spec.n_pulses):
+        o.push_pulse(d[p], p)
+        r.push_pulse(d[p], p)
+        o.reconstruct(m)
+        r.reconstruct(m)
+        n = p + 1
+        assert 1 + n * m / 2 <= o.t <= 1 + n * m
+        assert 1 + m / 2 <= r.t <= 1 + m
+    # one step per pulse: t_2 = phi (t^2 = t + 1), then t_3 solves t^2 - t = phi^2 = phi + 1
+    e = OnlineFistaOracle.from_workload(wl)
+    phi = (1 + math.sqrt(5)) / 2
+    e.push_pulse(d[0], 0)
+    e.reconstruct(1)
+    assert math.isclose(e.t, phi, rel_tol=1e-15)
+    e.push_pulse(d[1], 1)
+    e.reconstruct(1)
+    assert math.isclose(e.t, (1 + math.sqrt(5 + 4 * phi)) / 2, rel_tol=1e-15)
+
+
+def _prox_polar(u, alpha):
+    """argmin_x 1/2|x - u|^2 + alpha|x| per entry, solved in polar form:
+    keep the phase of u, modulus max(|u| - alpha, 0)."""
+    out = np.zeros_like(u)
+    for i, ui in enumerate(u):
+        r = abs(ui)
+        if r > alpha:
+            out[i] = (r - alpha) * (ui / r)
+    return out
+
+
+def test_warm_started_steps_by_hand():
+    """The first step of pulse n is the forward-backward step from
+    z_1 = c_hat_{n-1}; the second extrapolates with beta = (t - 1)/t' from the
+    carried t = t_{n-1}.  Both written out here from (c_hat_{n-1}, H_n, b_n)."""
+    wl = tiny(n_pulses=5)
+    d = sar.echoes(wl)
+    o = OnlineFistaOracle.from_workload(wl)
+    for p in range(4):
+        o.push_pulse(d[p], p)
+        o.reconstruct(20)
+    o.push_pulse(d[4], 4)
+    c0, t0 = o.c.copy(), o.t
+    H, b, tau, alpha = o.H.copy(), o.b.copy(), o.tau, o.lam * o.tau
+    assert np.abs(c0).max() > 0
+    c1 = _prox_polar(c0 - tau * (H @ c0 - b), alpha)
+    t1 = (1 + math.sqrt(1 + 4 * t0 * t0)) / 2
+    z2 = c1 + (t0 - 1) / t1 * (c1 - c0)
+    c2 = _prox_polar(z2 - tau * (H @ z2 - b), alpha)
+    keep = (o.c.copy(), o.t, o.w.copy(), o.rho_hat, o.sigma2_acc)
+    o.reconstruct(1)
+    assert np.allclose(o.c, c1, atol=1e-13 * np.abs(c1).max(), rtol=0)
+    o.c, o.t, o.w, o.rho_hat, o.sigma2_acc = keep
+    o.reconstruct(2)
+    assert np.allclose(o.c, c2, atol=1e-13 * np.abs(c2).max(), rtol=0)
+    # a cold start (z_1 = 0) is a different point
+    cold = _prox_polar(tau * b, alpha)
+    assert np.linalg.norm(cold - c1) > 1e-3 * np.linalg.norm(c1)
+
+
+def test_phase_correction_undoes_the_phase_error():
+    """Section II with a per-pulse phase error: d_s = e^{i phi_s} F_s rho.  Pushing
+    it with the correction phi_hat_s = phi_s (data used as d_s e^{-i phi_hat_s})
+    reproduces the error-free run; the opposite sign does not."""
+    s = spec("autofocus", n_side=8, patch_m=8.0, n_pulses=6, n_freq=16, n_points=3,
+             n_lines=0, inner_steps=10)
+    wl = make_workload(s)
+    assert np.abs(wl.phase_err).max() > 0.1
+    d_err = sar.echoes(wl, with_noise=False, with_phase_error=True)
+    d_ok = sar.echoes(wl, with_noise=False, with_phase_error=False)
+    a = OnlineFistaOracle.from_workload(wl)
+    b = OnlineFistaOracle.from_workload(wl)
+    c = OnlineFistaOracle.from_workload(wl)
+    for p in range(s.n_pulses):
+        a.push_pulse(d_ok[p], p)
+        b.push_pulse(d_err[p], p, wl.phase_err[p])
+        c.push_pulse(d_err[p], p, -wl.phase_err[p])
+        for o in (a, b, c):
+            o.reconstruct(s.inner_steps)
+    assert np.allclose(b.b, a.b, atol=1e-12 * np.abs(a.b).max(), rtol=0)
+    assert np.allclose(b.c, a.c, atol=1e-12 * np.abs(a.c).max(), rtol=0)
+    assert np.linalg.norm(c.c - a.c) > 1e-2 * np.linalg.norm(a.c)
 
 
 # ---------------------------------------------------------------- fixed points
