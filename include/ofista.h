@@ -75,11 +75,18 @@ enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1, OFISTA_DICT_EDGELET = 2
    each operand (three products, FP32 accumulation; needs n_freq divisible by
    32, else OFISTA_E_UNSUPPORTED). */
 enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
-/* L_n rule: RUNNING = rho_{n-1} + sigma_n^2 (rho: Rayleigh quotient of a power
-   vector advanced once per FISTA step on the current H); BOUND = L_{n-1} +
-   sigma_n^2 (the incremental bound of Section III-C taken literally).
-   sigma_n^2 = ||A_s||_2^2 from an FP64 power iteration (at most 200 steps,
-   stop at 1e-13 relative change of the Rayleigh quotient, start 1/sqrt(K)). */
+/* L_n rule (Section III-B asks for L >= ||sum G^H G||_2; Section III-C bounds
+   its growth by ||G_n||_2^2 per pulse):
+   RUNNING = rho + the sum of sigma^2 over the pulses pushed since the last
+     FISTA step (rho: Rayleigh quotient of a power vector advanced once per
+     FISTA step on that step's H; 0 before any step), so several pushes
+     between reconstructions each add their increment;
+   BOUND = L_{n-1} + sigma_n^2 (the incremental bound taken literally).
+   sigma_n^2 = ||A_s||_2^2 = lambda_max(A_s A_s^H), computed for every
+   position at ofista_create in FP64 to rounding: bisection on a
+   positive-definiteness test (Levinson-Durbin on the Toeplitz A_s A_s^H of
+   the identity and Haar dictionaries; Householder tridiagonalisation and
+   Sturm counts for the edgelet dictionary), taking the upper end. */
 enum { OFISTA_LIP_RUNNING = 0, OFISTA_LIP_BOUND = 1 };
 /* What the state keeps (Section III-D, Table I).  GRAM: the running sufficient
    statistics H_n, b_n (Online FISTA).  PULSES: the comparator that keeps every

@@ -297,16 +297,20 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
   reinterpret_cast<float *>(a.Q + slot_index(J0, I, a.nb) * kTile + row0)[lane] = v[0];
 }
 
-// Per-pulse scalars: lambda (first pulse), sigma^2 of position s, rho_{n-1}
-// from the power-vector slots, L_n, tau, alpha.  One 256-thread workgroup;
-// the slot sums use the same fixed-order tree as the step epilogue.
+// Per-pulse scalars: lambda (first pulse), sigma^2 of position s, L_n, tau,
+// alpha.  L_n (RUNNING) = rho + the sigma^2 of every pulse pushed since the
+// last FISTA step (Weyl: lambda_max(H + sum dH) <= lambda_max(H) + sum
+// ||dH||_2), rho the Rayleigh quotient of that step's power vector, formed
+// here from its slots when steps ran since the previous push (new_rho) and
+// kept from then on otherwise.  BOUND: L_{n-1} + sigma_n^2.  One 256-thread
+// workgroup; the slot sums use the same fixed-order tree as the step epilogue.
 __global__ __launch_bounds__(256) void k_scalars(DevScalars *scal, const double *sig2, int s,
                                                  int first, int rel, double lam_in, int lip,
-                                                 int have_rho, const double *slot_r,
+                                                 int new_rho, const double *slot_r,
                                                  const double *slot_m, int nparts) {
   __shared__ double red[256];
   double rho = 0.0;
-  if (have_rho) {
+  if (new_rho) {
     double pr = 0.0, pm = 0.0;
     for (int j = threadIdx.x; j < nparts; j += 256) {
       pr += slot_r[j];
@@ -321,9 +325,16 @@ __global__ __launch_bounds__(256) void k_scalars(DevScalars *scal, const double 
     scal->lam = rel ? lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : lam_in;
   }
   const double sigma2 = sig2[s];
-  const double L = lip == 0 ? rho + sigma2 : scal->L + sigma2;
+  double acc = sigma2;
+  if (new_rho) {
+    scal->rho = rho;
+  } else {
+    rho = scal->rho;
+    acc += scal->sig2_acc;
+  }
+  const double L = lip == 0 ? rho + acc : scal->L + sigma2;
+  scal->sig2_acc = acc;
   scal->sigma2 = sigma2;
-  scal->rho = rho;
   scal->L = L;
   scal->tau = 1.0 / L;
   scal->alpha = scal->lam / L;
@@ -528,10 +539,10 @@ hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, flo
 }
 
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
-                          double lam_in, int lip, int have_rho, const double *slot_r,
+                          double lam_in, int lip, int new_rho, const double *slot_r,
                           const double *slot_m, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, st, scal, sig2, s, first, rel, lam_in,
-                     lip, have_rho, slot_r, slot_m, nparts);
+                     lip, new_rho, slot_r, slot_m, nparts);
   return hipGetLastError();
 }
 

@@ -51,10 +51,11 @@ struct DevScalars {
   double tau;           // 1 / L_n
   double alpha;         // lam * tau, the shrink threshold
   double sigma2;        // ||A_s||_2^2 of the last pushed pulse
-  double rho;           // rho_{n-1} used for the last L_n
+  double rho;           // Rayleigh quotient of the last FISTA step before the last push
   unsigned dbmax_bits;  // max_i |Delta b_i| of the first pulse, float bits
   unsigned pad0;
-  double pad1[2];
+  double sig2_acc;      // sum of sigma^2 of the pulses pushed since that step
+  double pad1;
 };
 
 // Geometry passed by value.  N is the coefficient count M (the length of b,
@@ -126,13 +127,18 @@ hipError_t launch_echo(const Geom &g, const double *pos, int s,
                        const float2 *rho, const float2 *noise, double snr_db,
                        double phase_err, double2 *tmp, float2 *out,
                        hipStream_t st);
+// sigma^2 = ||A_s||_2^2 for every position (identity and Haar dictionaries,
+// where A_s A_s^H is Hermitian Toeplitz): FP64 generator, then bisection with
+// a Levinson-Durbin definiteness test.
 hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
                          double *sig2, hipStream_t st);
 // Dense route to sigma^2 (any dictionary): G = A A^H (K x K, FP64 sums) from
-// the K x Npad rows A, then FP64 power iteration on nmat such matrices stored
-// back to back, one workgroup each, results to sig2[0 .. nmat).
+// the K x Npad rows A, then the largest eigenvalue of nmat such matrices
+// stored back to back (FP64 Householder tridiagonalisation in place -- the
+// matrices are destroyed -- and Sturm bisection), one workgroup each, results
+// to sig2[0 .. nmat).
 hipError_t launch_gram_kk(const Geom &g, const float2 *A, double2 *G, hipStream_t st);
-hipError_t launch_power_dense(int K, const double2 *G, int nmat, double *sig2, hipStream_t st);
+hipError_t launch_sigma2_dense(int K, double2 *G, int nmat, double *sig2, hipStream_t st);
 
 // ---- gram.hip ----
 // Correlation as its own launch (split-BF16 path): b += A^H (d e^{-i phi}).
@@ -224,7 +230,7 @@ hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, flo
                          hipStream_t st);
 hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
                           int first, int rel, double lam_in, int lip,
-                          int have_rho, const double *slot_r,
+                          int new_rho, const double *slot_r,
                           const double *slot_m, int nparts, hipStream_t st);
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
 // *count (zeroed by the caller) += #{m < M : |c_m| > thr} (FP32 magnitude).

@@ -250,7 +250,10 @@ constexpr int kToepDCh = 8;  // lags per workgroup
 
 // Toeplitz generator of A_s A_s^H for a uniform frequency grid:
 // (A_s A_s^H)[k, l] = g(k - l), g(d) = sum_i exp(-i 4 pi d df R_i / c0), g(-d) = conj(g(d)).
-// W W^T = I for both dictionaries, so the pixel-domain kernel suffices.
+// W W^T = I for both dictionaries, so the pixel-domain kernel suffices.  The
+// phasors are FP64: the first lag of a thread's chunk from an FP64 sincos of
+// its whole phase (at most ~2e5 rad, so ~2e-11 rad of rounding), the next ones
+// by multiplying with the one-lag phasor (one rounding each).
 __global__ __launch_bounds__(256) void k_toeplitz(Geom g, const double *__restrict__ pos,
                                                   double2 *__restrict__ gtoep) {
   __shared__ double2 red[256];
@@ -262,12 +265,19 @@ __global__ __launch_bounds__(256) void k_toeplitz(Geom g, const double *__restri
 #pragma unroll
   for (int j = 0; j < kToepDCh; ++j) acc[j] = make_double2(0.0, 0.0);
   for (int i = threadIdx.x; i < g.npix; i += 256) {
-    const double R = pixel_range(g, p, i);
+    const double th = c4d * pixel_range(g, p, i);
+    double s1, c1, s0, c0;
+    sincos(th, &s1, &c1);
+    sincos(th * d0, &s0, &c0);
+    double er = c0, ei = -s0;  // exp(-i d0 th)
 #pragma unroll
     for (int j = 0; j < kToepDCh; ++j) {
-      const float2 e = phasor_neg((c4d * (d0 + j)) * R);
-      acc[j].x += e.x;
-      acc[j].y += e.y;
+      acc[j].x += er;
+      acc[j].y += ei;
+      const double nr = er * c1 + ei * s1;  // times exp(-i th)
+      const double ni = ei * c1 - er * s1;
+      er = nr;
+      ei = ni;
     }
   }
   for (int j = 0; j < kToepDCh; ++j) {
@@ -276,61 +286,127 @@ __global__ __launch_bounds__(256) void k_toeplitz(Geom g, const double *__restri
   }
 }
 
-constexpr int kPowerMaxSteps = 200;
-constexpr double kPowerRelTol = 1e-13;
+// ---------------------------------------------------------------------------
+// sigma^2 = ||A_s||_2^2 = lambda_max(T) exactly (to FP64 rounding), by
+// bisection on mu with the test "mu I - T is positive definite".  The top of
+// this spectrum is tightly clustered (lambda_2 / lambda_1 ~ 1 - 1e-7 on the
+// workload geometries), which rules out power iteration.  The bracket's upper
+// end is returned, so the result is an upper bound up to the rounding of the
+// test.
 
-// sigma^2 = lambda_max(A_s A_s^H) by FP64 power iteration, one workgroup per
-// position: v0 = 1/sqrt(K); y = M v, q = Re(v^H y); stop when |q - q_prev| <=
-// 1e-13 |q| or after 200 steps; otherwise v = y / |y|.
-__global__ __launch_bounds__(256) void k_power_sigma2(int K, const double2 *__restrict__ gtoep,
-                                                      double *__restrict__ sig2) {
-  extern __shared__ double2 sh[];
-  double2 *gl = sh;          // K
-  double2 *v = sh + K;       // K
-  double2 *y = sh + 2 * K;   // K
-  __shared__ double2 red[256];
-  __shared__ int done;
-  const int s = blockIdx.x;
-  for (int k = threadIdx.x; k < K; k += 256) {
-    gl[k] = gtoep[static_cast<size_t>(s) * K + k];
-    v[k] = make_double2(1.0 / sqrt(static_cast<double>(K)), 0.0);
-  }
-  if (threadIdx.x == 0) done = 0;
-  __syncthreads();
-  double q = 0.0, q_prev = 0.0;
-  for (int step = 0; step < kPowerMaxSteps; ++step) {
-    double2 part = make_double2(0.0, 0.0);  // (Re v^H y, |y|^2)
-    for (int k = threadIdx.x; k < K; k += 256) {
-      double re = 0.0, im = 0.0;
-      for (int l = 0; l <= k; ++l) {  // M[k, l] = g(k - l)
-        const double2 m = gl[k - l], x = v[l];
-        re += m.x * x.x - m.y * x.y;
-        im += m.x * x.y + m.y * x.x;
-      }
-      for (int l = k + 1; l < K; ++l) {  // M[k, l] = conj(g(l - k))
-        const double2 m = gl[l - k], x = v[l];
-        re += m.x * x.x + m.y * x.y;
-        im += m.x * x.y - m.y * x.x;
-      }
-      y[k] = make_double2(re, im);
-      part.x += v[k].x * re + v[k].y * im;
-      part.y += re * re + im * im;
-    }
-    const double2 tot = block_sum_d2(part, red);
-    q = tot.x;
-    if (threadIdx.x == 0) {
-      if ((step > 0 && fabs(q - q_prev) <= kPowerRelTol * fabs(q)) || tot.y == 0.0) done = 1;
-    }
-    __syncthreads();
-    if (done) break;
-    q_prev = q;
-    const double inv = 1.0 / sqrt(tot.y);
-    for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(y[k].x * inv, y[k].y * inv);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sig2[s] = q;
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// mu I - T positive definite?  T Hermitian Toeplitz with first column r
+// (T[k, 0] = r[k]).  Levinson-Durbin on S = mu I - T: the prediction-error
+// powers E_k are the pivots of S = L D L^H, so S is positive definite exactly
+// when every E_k > 0; the recursion stops at the first E_k <= 0 (only the
+// leading minors up to that order were needed, and they were definite, so the
+// recursion was stable up to there).  One wavefront; a (the predictor,
+// a[1..K-1]) lives in LDS and is updated in pairs (j, k - j), one lane per
+// pair.
+__device__ bool levinson_definite(int K, const double2 *__restrict__ r, double mu,
+                                  double2 *__restrict__ a, int lane) {
+  double E = mu - r[0].x;
+  if (!(E > 0.0)) return false;
+  for (int k = 1; k < K; ++k) {
+    // acc = s(k) + sum_{j=1}^{k-1} a_j s(k - j),  s(d) = -r(d) for d >= 1
+    double pr = 0.0, pi = 0.0;
+    for (int j = 1 + lane; j < k; j += 64) {
+      const double2 x = a[j], y = r[k - j];
+      pr -= x.x * y.x - x.y * y.y;
+      pi -= x.x * y.y + x.y * y.x;
+    }
+    pr = wave_sum_f64(pr) - r[k].x;
+    pi = wave_sum_f64(pi) - r[k].y;
+    const double kr = -pr / E, ki = -pi / E;  // kappa = -acc / E
+    const double m2 = kr * kr + ki * ki;
+    const double En = E * (1.0 - m2);
+    // a_j <- a_j + kappa conj(a_{k-j}), j = 1..k-1, then a_k = kappa
+    for (int j = 1 + lane; 2 * j <= k; j += 64) {
+      const int jj = k - j;
+      const double2 x = a[j];
+      if (jj == j) {
+        a[j] = make_double2(x.x + kr * x.x + ki * x.y, x.y + ki * x.x - kr * x.y);
+      } else {
+        const double2 y = a[jj];
+        a[j] = make_double2(x.x + kr * y.x + ki * y.y, x.y + ki * y.x - kr * y.y);
+        a[jj] = make_double2(y.x + kr * x.x + ki * x.y, y.y + ki * x.x - kr * x.y);
+      }
+    }
+    if (lane == 0) a[k] = make_double2(kr, ki);
+    wave_sync_lds();
+    E = En;
+    if (!(E > 0.0)) return false;
+  }
+  return true;
+}
+
+constexpr int kSectWaves = 4;     // trial points per bisection round at most (one per wave)
+constexpr int kSectRounds = 96;   // rounds at most (a 3-section gains 1.58 bits per round)
+constexpr size_t kSectLds = 60 * 1024;  // dynamic LDS budget (generator + predictors)
+
+// Trial waves that fit the LDS budget next to the K-entry generator.
+inline int sect_waves(int K) {
+  const size_t per = static_cast<size_t>(K) * sizeof(double2);
+  const int fit = static_cast<int>(kSectLds / per) - 1;
+  return fit < 1 ? 1 : (fit > kSectWaves ? kSectWaves : fit);
+}
+
+// One workgroup per position.  Bracket: lambda_max >= T[0, 0]; every row sum
+// of |T| is at most |g(0)| + 2 sum_{d >= 1} |g(d)|.  Each round the first nw
+// waves test the nw interior points of an (nw + 1)-section and the bracket
+// shrinks to the first definite one.
+__global__ __launch_bounds__(256) void k_sigma2_toeplitz(int K, int nw,
+                                                         const double2 *__restrict__ gtoep,
+                                                         double *__restrict__ sig2) {
+  extern __shared__ double2 sh[];
+  double2 *r = sh;                                      // K
+  double2 *apred = sh + K + (threadIdx.x >> 6) * K;     // K per trial wave
+  __shared__ double red[256];
+  __shared__ int pd[kSectWaves];
+  const int s = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double gs = 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const double2 v = gtoep[static_cast<size_t>(s) * K + k];
+    r[k] = v;
+    gs += (k == 0 ? 1.0 : 2.0) * sqrt(v.x * v.x + v.y * v.y);
+  }
+  red[threadIdx.x] = gs;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  double lo = r[0].x;
+  double hi = red[0] * (1.0 + 1e-14);
+  __syncthreads();
+  for (int round = 0; round < kSectRounds && hi - lo > 1e-15 * hi; ++round) {
+    if (wave < nw) {
+      const double mu = lo + (hi - lo) * (wave + 1) / (nw + 1);
+      const bool ok = mu > lo && mu < hi ? levinson_definite(K, r, mu, apred, lane) : mu >= hi;
+      if (lane == 0) pd[wave] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    int w = 0;
+    while (w < nw && !pd[w]) ++w;
+    const double nlo = w == 0 ? lo : lo + (hi - lo) * w / (nw + 1);
+    const double nhi = w == nw ? hi : lo + (hi - lo) * (w + 1) / (nw + 1);
+    __syncthreads();
+    if (!(nlo > lo || nhi < hi)) break;  // no representable progress left
+    lo = nlo;
+    hi = nhi;
+  }
+  if (threadIdx.x == 0) sig2[s] = hi;
+}
 
 // ---------------------------------------------------------------------------
 // Edgelet dictionary (Section III-A): binary atoms, so A_s = F_s W is a
@@ -468,60 +544,129 @@ __global__ __launch_bounds__(256) void k_gram_kk(int K, int Npad, int M,
   if (k < K && l < K) G[static_cast<size_t>(k) * K + l] = make_double2(re, im);
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-// sigma^2 = lambda_max(G) for a dense Hermitian K x K matrix, FP64 power
-// iteration with the same start and stopping rule as k_power_sigma2.  One
-// workgroup per matrix; wave w forms y_k for rows k = w, w + 4, ... with the
-// lanes striding over l (coalesced rows) and a fixed-order wave sum.
-__global__ __launch_bounds__(256) void k_power_dense(int K, const double2 *__restrict__ Gall,
-                                                     double *__restrict__ sig2) {
+// sigma^2 = lambda_max(G) for a dense Hermitian K x K matrix (the edgelet
+// dictionary, where A_s A_s^H is not Toeplitz): Householder reduction to a
+// Hermitian tridiagonal matrix in FP64, in place, then bisection on the
+// Sturm count of the equivalent real tridiagonal (off-diagonals |e_k|).  One
+// workgroup per matrix.  Step k reflects the column below the diagonal,
+// x = G[k+1:, k], onto alpha e_1 with alpha = -e^{i arg x_0} |x|:
+// v = x - alpha e_1, beta = 2 / |v|^2, p = beta G22 v, w = p - (beta/2)(v^H p) v,
+// G22 <- G22 - v w^H - w v^H.  Only the trailing block is kept up to date.
+__global__ __launch_bounds__(256) void k_sigma2_dense(int K, double2 *__restrict__ Gall,
+                                                      double *__restrict__ sig2) {
   extern __shared__ double2 sh[];
-  double2 *v = sh;       // K
-  double2 *y = sh + K;   // K
+  double2 *v = sh;                                       // K
+  double2 *w = sh + K;                                   // K
+  double *dg = reinterpret_cast<double *>(sh + 2 * K);   // K diagonal
+  double *e2 = dg + K;                                   // K squared off-diagonals
   __shared__ double2 red[256];
-  __shared__ int done;
-  const double2 *G = Gall + static_cast<size_t>(blockIdx.x) * K * K;
+  __shared__ double bounds[2];
+  double2 *G = Gall + static_cast<size_t>(blockIdx.x) * K * K;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(1.0 / sqrt(static_cast<double>(K)), 0.0);
-  if (threadIdx.x == 0) done = 0;
-  __syncthreads();
-  double q = 0.0, q_prev = 0.0;
-  for (int step = 0; step < kPowerMaxSteps; ++step) {
-    for (int k = wave; k < K; k += 4) {
+  for (int k = 0; k + 2 < K; ++k) {
+    const int m0 = k + 1;
+    // x_i = G[i, k] = conj(G[k, i]) (row k is contiguous)
+    double2 part = make_double2(0.0, 0.0);
+    for (int i = m0 + threadIdx.x; i < K; i += 256) {
+      const double2 g = G[static_cast<size_t>(k) * K + i];
+      v[i] = make_double2(g.x, -g.y);
+      part.x += g.x * g.x + g.y * g.y;
+    }
+    const double xn2 = block_sum_d2(part, red).x;  // also orders the v stores
+    const double2 x0 = v[m0];
+    const double a0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+    if (threadIdx.x == 0) {
+      dg[k] = G[static_cast<size_t>(k) * K + k].x;
+      e2[k] = xn2;
+    }
+    if (!(xn2 - a0 * a0 > 0.0)) {  // already tridiagonal in this column
+      __syncthreads();
+      continue;
+    }
+    const double xn = sqrt(xn2);
+    const double ur = a0 > 0.0 ? x0.x / a0 : 1.0, ui = a0 > 0.0 ? x0.y / a0 : 0.0;
+    const double beta = 1.0 / (xn2 + xn * a0);  // 2 / |v|^2
+    __syncthreads();
+    if (threadIdx.x == 0) v[m0] = make_double2(x0.x + ur * xn, x0.y + ui * xn);
+    __syncthreads();
+    // p = beta G22 v: wave per row, lanes along the row
+    for (int i = m0 + wave; i < K; i += 4) {
       double re = 0.0, im = 0.0;
-      for (int l = lane; l < K; l += 64) {
-        const double2 m = G[static_cast<size_t>(k) * K + l], x = v[l];
-        re += m.x * x.x - m.y * x.y;
-        im += m.x * x.y + m.y * x.x;
+      for (int j = m0 + lane; j < K; j += 64) {
+        const double2 g = G[static_cast<size_t>(i) * K + j], y = v[j];
+        re += g.x * y.x - g.y * y.y;
+        im += g.x * y.y + g.y * y.x;
       }
       re = wave_sum_f64(re);
       im = wave_sum_f64(im);
-      if (lane == 0) y[k] = make_double2(re, im);
+      if (lane == 0) w[i] = make_double2(beta * re, beta * im);
     }
     __syncthreads();
-    double2 part = make_double2(0.0, 0.0);  // (Re v^H y, |y|^2)
-    for (int k = threadIdx.x; k < K; k += 256) {
-      part.x += v[k].x * y[k].x + v[k].y * y[k].y;
-      part.y += y[k].x * y[k].x + y[k].y * y[k].y;
-    }
-    const double2 tot = block_sum_d2(part, red);
-    q = tot.x;
-    if (threadIdx.x == 0) {
-      if ((step > 0 && fabs(q - q_prev) <= kPowerRelTol * fabs(q)) || tot.y == 0.0) done = 1;
-    }
+    part = make_double2(0.0, 0.0);
+    for (int i = m0 + threadIdx.x; i < K; i += 256)  // Re(v^H p)
+      part.x += v[i].x * w[i].x + v[i].y * w[i].y;
+    const double kc = 0.5 * beta * block_sum_d2(part, red).x;
+    for (int i = m0 + threadIdx.x; i < K; i += 256)
+      w[i] = make_double2(w[i].x - kc * v[i].x, w[i].y - kc * v[i].y);
     __syncthreads();
-    if (done) break;
-    q_prev = q;
-    const double inv = 1.0 / sqrt(tot.y);
-    for (int k = threadIdx.x; k < K; k += 256) v[k] = make_double2(y[k].x * inv, y[k].y * inv);
+    // G22 -= v w^H + w v^H
+    const int m = K - m0;
+    for (int e = threadIdx.x; e < m * m; e += 256) {
+      const int i = m0 + e / m, j = m0 + e % m;
+      const double2 vi = v[i], wi = w[i], vj = v[j], wj = w[j];
+      double2 &g = G[static_cast<size_t>(i) * K + j];
+      g.x -= (vi.x * wj.x + vi.y * wj.y) + (wi.x * vj.x + wi.y * vj.y);
+      g.y -= (vi.y * wj.x - vi.x * wj.y) + (wi.y * vj.x - wi.x * vj.y);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) sig2[blockIdx.x] = q;
+  if (threadIdx.x == 0) {
+    if (K >= 2) {
+      const double2 g = G[static_cast<size_t>(K - 1) * K + (K - 2)];
+      dg[K - 2] = G[static_cast<size_t>(K - 2) * K + (K - 2)].x;
+      e2[K - 2] = g.x * g.x + g.y * g.y;
+    }
+    dg[K - 1] = G[static_cast<size_t>(K - 1) * K + (K - 1)].x;
+    // bracket: lambda_max >= max diagonal; Gershgorin for the upper end
+    double lo = dg[0], hi = -1e300;
+    for (int i = 0; i < K; ++i) {
+      const double el = i > 0 ? sqrt(e2[i - 1]) : 0.0, er = i + 1 < K ? sqrt(e2[i]) : 0.0;
+      lo = fmax(lo, dg[i]);
+      hi = fmax(hi, dg[i] + el + er);
+    }
+    bounds[0] = lo;
+    bounds[1] = hi * (1.0 + 1e-14) + 1e-300;
+  }
+  __syncthreads();
+  // 256-section rounds: thread t tests lo + (hi - lo)(t + 1)/257 with the
+  // Sturm count (number of eigenvalues below mu = number of negative pivots
+  // of T - mu I); "all K below" means mu is above lambda_max.
+  __shared__ int below[256];
+  double lo = bounds[0], hi = bounds[1];
+  for (int round = 0; round < 12 && hi - lo > 1e-15 * fabs(hi); ++round) {
+    const double mu = lo + (hi - lo) * (threadIdx.x + 1) / 257.0;
+    int cnt = 0;
+    double q = dg[0] - mu;
+    const double tiny = 1e-300;
+    if (q == 0.0) q = -tiny;
+    cnt += q < 0.0;
+    for (int i = 1; i < K; ++i) {
+      q = dg[i] - mu - e2[i - 1] / q;
+      if (q == 0.0) q = -tiny;
+      cnt += q < 0.0;
+    }
+    below[threadIdx.x] = (mu > lo && mu < hi) ? (cnt == K) : (mu >= hi);
+    __syncthreads();
+    int t = 0;
+    while (t < 256 && !below[t]) ++t;
+    const double nlo = t == 0 ? lo : lo + (hi - lo) * t / 257.0;
+    const double nhi = t == 256 ? hi : lo + (hi - lo) * (t + 1) / 257.0;
+    __syncthreads();
+    if (!(nlo > lo || nhi < hi)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (threadIdx.x == 0) sig2[blockIdx.x] = hi;
 }
 
 }  // namespace
@@ -591,8 +736,9 @@ hipError_t launch_sigma2(const Geom &g, const double *pos, double2 *gtoep,
                          double *sig2, hipStream_t st) {
   dim3 grid(g.npos, (g.K + kToepDCh - 1) / kToepDCh);
   hipLaunchKernelGGL(k_toeplitz, grid, dim3(256), 0, st, g, pos, gtoep);
-  const size_t lds = 3 * static_cast<size_t>(g.K) * sizeof(double2);
-  hipLaunchKernelGGL(k_power_sigma2, dim3(g.npos), dim3(256), lds, st, g.K, gtoep, sig2);
+  const int nw = sect_waves(g.K);
+  const size_t lds = (1 + nw) * static_cast<size_t>(g.K) * sizeof(double2);
+  hipLaunchKernelGGL(k_sigma2_toeplitz, dim3(g.npos), dim3(256), lds, st, g.K, nw, gtoep, sig2);
   return hipGetLastError();
 }
 
@@ -602,10 +748,10 @@ hipError_t launch_gram_kk(const Geom &g, const float2 *A, double2 *G, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_power_dense(int K, const double2 *G, int nmat, double *sig2, hipStream_t st) {
+hipError_t launch_sigma2_dense(int K, double2 *G, int nmat, double *sig2, hipStream_t st) {
   if (nmat <= 0) return hipSuccess;
-  const size_t lds = 2 * static_cast<size_t>(K) * sizeof(double2);
-  hipLaunchKernelGGL(k_power_dense, dim3(nmat), dim3(256), lds, st, K, G, sig2);
+  const size_t lds = 2 * static_cast<size_t>(K) * (sizeof(double2) + sizeof(double));
+  hipLaunchKernelGGL(k_sigma2_dense, dim3(nmat), dim3(256), lds, st, K, G, sig2);
   return hipGetLastError();
 }
 

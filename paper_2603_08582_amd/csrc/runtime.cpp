@@ -386,6 +386,7 @@ struct ofista_ctx {
   int64_t n = 0;       // pulses since reset
   int64_t G = 0;       // FISTA steps since reset
   bool have_iter = false;
+  bool step_since_push = false;  // a FISTA step ran after the last push
   double t = 1.0;
   // differentiation form: what was pushed, and the segment being re-run
   struct PulseRec {
@@ -478,6 +479,7 @@ ofista_status do_reset(ofista_ctx *c) {
   c->n = 0;
   c->G = 0;
   c->have_iter = false;
+  c->step_since_push = false;
   c->t = 1.0;
   c->rec.clear();
   return OFISTA_OK;
@@ -708,8 +710,8 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
             (e = launch_gram_kk(g, d.A, Gs + static_cast<size_t>(j) * per, c->st)) != hipSuccess)
           return fail(e, "sigma2 rows");
       }
-      if ((e = launch_power_dense(L.K, Gs, nm, d.sig2 + s0, c->st)) != hipSuccess)
-        return fail(e, "sigma2 power iteration");
+      if ((e = launch_sigma2_dense(L.K, Gs, nm, d.sig2 + s0, c->st)) != hipSuccess)
+        return fail(e, "sigma2 eigenvalue");
     }
   } else if ((e = launch_sigma2(g, d.pos, d.gtoep, d.sig2, c->st)) != hipSuccess) {
     return fail(e, "sigma2 kernels");
@@ -782,8 +784,9 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
     ProfScope p(c, kProfScalars);
     const int par = static_cast<int>(c->G & 1);
     OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
-                            c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
-                            L.nparts, c->st));
+                            c->cfg.lipschitz, c->step_since_push ? 1 : 0, d.slots[par],
+                            d.slots[par ^ 1], L.nparts, c->st));
+    c->step_since_push = false;
   }
   if (seg_j >= 0) {
     const size_t hbytes = L.ntiles * kTile * kTile * sizeof(float2);
@@ -822,8 +825,9 @@ ofista_status push_store(ofista_ctx *c, const void *d_pulse, int32_t s, double p
     ProfScope p(c, kProfScalars);
     const int par = static_cast<int>(c->G & 1);
     OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
-                            c->cfg.lipschitz, c->have_iter ? 1 : 0, d.slots[par], d.slots[par ^ 1],
-                            L.nparts, c->st));
+                            c->cfg.lipschitz, c->step_since_push ? 1 : 0, d.slots[par],
+                            d.slots[par ^ 1], L.nparts, c->st));
+    c->step_since_push = false;
   }
   c->n += 1;
   return OFISTA_OK;
@@ -890,7 +894,7 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     t = tn;
   }
   c->t = t;
-  if (iters > 0) c->have_iter = true;
+  if (iters > 0) c->have_iter = c->step_since_push = true;
   if (d_coef_out) {
     OF_CK(c, hipMemcpyAsync(d_coef_out, d.cbuf[c->G & 1], static_cast<size_t>(L.N) * sizeof(float2),
                             hipMemcpyDeviceToDevice, c->st));
@@ -1224,6 +1228,7 @@ ofista_status export_to(ofista_ctx *c, void *d_buf) {
   hdr[1] = static_cast<double>(c->G);
   hdr[2] = c->t;
   hdr[3] = c->have_iter ? 1.0 : 0.0;
+  hdr[6] = c->step_since_push ? 1.0 : 0.0;
   hdr[4] = static_cast<double>(L.N);
   hdr[5] = static_cast<double>(L.K);
   char *o = static_cast<char *>(d_buf);
@@ -1261,6 +1266,7 @@ ofista_status import_from(ofista_ctx *c, const void *d_buf) {
   c->G = static_cast<int64_t>(hdr[1]);
   c->t = hdr[2];
   c->have_iter = hdr[3] != 0.0;
+  c->step_since_push = hdr[6] != 0.0;
   const int par = static_cast<int>(c->G & 1);
   const size_t vec = static_cast<size_t>(L.Npad) * sizeof(float2);
   o += align_up(sizeof(hdr));

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import sar
-from oracle.online_fista import power_sigma2
+from oracle.online_fista import spectral_norm_sq
 from workload import library_kwargs, make_workload
 
 pytestmark = pytest.mark.gpu
@@ -115,9 +115,11 @@ def test_large_full_run_sampled_entries():
     # sigma^2 of sample positions, from the state after pushing them again
     for pos in (0, P // 2, P - 1):
         F = sar.forward_rows(wl.positions[pos], pix, wl.freqs())
-        ref = power_sigma2(F @ F.conj().T)
+        ref = spectral_norm_sq(F)
         g.push_pulse(dd[pos], pos)
-        assert abs(g.state()["sigma2"] / ref - 1) < 1e-6
+        # FP64 on both sides; the oracle's F F^H carries ~4e-10 relative
+        # rounding from its ~4e6 rad phases
+        assert abs(g.state()["sigma2"] / ref - 1) < 3e-9
     x = g.image().cpu().numpy()
     assert np.all(np.isfinite(x))
     # the strongest scatterers are found
