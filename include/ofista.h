@@ -195,6 +195,23 @@ ofista_status ofista_push_pulse(struct ofista_ctx *ctx, const void *d_pulse,
 ofista_status ofista_reconstruct(struct ofista_ctx *ctx, int32_t iters,
                                  void *d_coef_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   as ofista_reconstruct -- same kernels, same order, bitwise the same result
+   -- but the FISTA step's matvec partials (nb x nb x 64 x 16 bytes, nb =
+   ceil(M / 64)) live in a fixed 16 MiB array in device memory that the library
+   holds on every GPU it runs on until the process ends, instead of in the
+   ctx's workspace.  Nothing in that array needs to start at zero (every step
+   reads only the partials it wrote).  Allocates nothing: no hipMalloc,
+   hipFree, event creation or host allocation (profiling events are not taken
+   in this call).  Every ctx on one GPU shares the array, so calls that
+   overlap on one GPU (different streams or threads) race and must be
+   serialised by the caller.  OFISTA_E_UNSUPPORTED when the partials exceed
+   the array (M > 8192) or with PULSES storage; otherwise the statuses of
+   ofista_reconstruct. */
+ofista_status ofista_reconstruct_static(struct ofista_ctx *ctx, int32_t iters,
+                                        void *d_coef_out);
+
 /* Image x = W c_hat (Section III-B, rho ~ H c with the paper's dictionary H).
    d_img_out: device, N complex64. */
 ofista_status ofista_image(struct ofista_ctx *ctx, void *d_img_out);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -15,7 +16,33 @@
 
 using namespace ofista;
 
+// Matvec partials of ofista_reconstruct_static: a fixed array in device
+// memory, one instance per GPU, alive until the process ends.  Host code never
+// passes the array's name to a kernel (it is a host-side stand-in there); it
+// uses the device address hipGetSymbolAddress returns for the current device.
+static constexpr size_t kStaticScratchBytes = size_t{16} << 20;  // nb <= 128 tile rows
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, resolved once.
+hipError_t static_scratch(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 
@@ -382,6 +409,9 @@ struct ofista_ctx {
   bool poisoned = false;
   hipError_t hip_err = hipSuccess;
   std::string msg;
+  // static detail for a non-HIP status of the last call (no allocation)
+  const char *note = nullptr;
+  ofista_status note_st = OFISTA_OK;
   // host-side state (all data independent)
   int64_t n = 0;       // pulses since reset
   int64_t G = 0;       // FISTA steps since reset
@@ -663,6 +693,10 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   };
   hipError_t e;
   if ((e = hipGetDevice(&c->device)) != hipSuccess) return fail(e, "hipGetDevice");
+  {
+    void *sp = nullptr;  // per-device static partials (ofista_reconstruct_static)
+    if ((e = static_scratch(c->device, &sp)) != hipSuccess) return fail(e, "hipGetSymbolAddress");
+  }
   if ((e = hipMemcpyAsync(d.pos, cfg->pos_xyz, 3 * sizeof(double) * L.npos, hipMemcpyHostToDevice, c->st)) != hipSuccess)
     return fail(e, "copy positions");
   if (!tij.empty() &&
@@ -835,7 +869,7 @@ ofista_status push_store(ofista_ctx *c, const void *d_pulse, int32_t s, double p
 
 // Algorithm 1 with `iters` steps; seg_j >= 0 also keeps u of every step.
 ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, int seg_j,
-                               double *t_start_out) {
+                               double *t_start_out, float4 *Q = nullptr) {
   const DevState &d = c->d;
   const Layout &L = c->L;
   double t = (c->n == 1 || c->cfg.momentum == OFISTA_MOMENTUM_RESTART) ? 1.0 : c->t;
@@ -853,7 +887,7 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.cn = d.cbuf[p ^ 1];
     a.zn = d.zbuf[p ^ 1];
     a.wn = d.wbuf[p ^ 1];
-    a.Q = d.Q;
+    a.Q = Q ? Q : d.Q;
     a.slot_prev = d.slots[p];
     a.slot_cur = d.slots[p ^ 1];
     a.scal = d.scal;
@@ -939,6 +973,47 @@ ofista_status ofista_reconstruct(ofista_ctx *c, int32_t iters, void *d_coef_out)
     if (iters > c->L.rec_iters) return OFISTA_E_ARG;
   }
   st = reconstruct_impl(c, iters, d_coef_out, -1, &t0);
+  if (st == OFISTA_OK && c->L.rec_every > 0) {
+    c->rec.back().iters = iters;
+    c->rec.back().t_start = t0;
+  }
+  return st;
+}
+
+ofista_status ofista_reconstruct_static(ofista_ctx *c, int32_t iters, void *d_coef_out) {
+  ofista_status st = usable(c);
+  if (st != OFISTA_OK) return st;
+  const Layout &L = c->L;
+  if (L.store) {
+    c->note = "ofista_reconstruct_static: PULSES storage has no matvec partials";
+    c->note_st = OFISTA_E_UNSUPPORTED;
+    return OFISTA_E_UNSUPPORTED;
+  }
+  const size_t need = static_cast<size_t>(L.nb) * L.nb * kTile * sizeof(float4);
+  if (need > kStaticScratchBytes) {
+    c->note = "ofista_reconstruct_static: the matvec partials exceed the 16 MiB static "
+              "array (at most 128 tile rows, M <= 8192)";
+    c->note_st = OFISTA_E_UNSUPPORTED;
+    return OFISTA_E_UNSUPPORTED;
+  }
+  if (iters < 0) return OFISTA_E_ARG;
+  if (c->n == 0) return OFISTA_E_STATE;
+  if (c->L.rec_every > 0) {
+    if (c->rec.empty() || c->rec.back().iters >= 0) return OFISTA_E_STATE;  // one per pulse
+    if (iters > c->L.rec_iters) return OFISTA_E_ARG;
+  }
+  void *sp = nullptr;  // resolved at create, so this only reads the table
+  if (static_scratch(c->device, &sp) != hipSuccess) {
+    c->note = "ofista_reconstruct_static: no static array on this device";
+    c->note_st = OFISTA_E_STATE;
+    return OFISTA_E_STATE;
+  }
+  // no profiling events here: taking one may create it
+  const bool prof = c->prof;
+  c->prof = false;
+  double t0 = 0.0;
+  st = reconstruct_impl(c, iters, d_coef_out, -1, &t0, static_cast<float4 *>(sp));
+  c->prof = prof;
   if (st == OFISTA_OK && c->L.rec_every > 0) {
     c->rec.back().iters = iters;
     c->rec.back().t_start = t0;
@@ -1354,6 +1429,7 @@ void ofista_destroy(ofista_ctx *c) {
 
 const char *ofista_error_string(const ofista_ctx *c, ofista_status st) {
   if (c && !c->msg.empty() && st == OFISTA_E_HIP) return c->msg.c_str();
+  if (c && c->note && st == c->note_st) return c->note;
   return status_text(st);
 }
 

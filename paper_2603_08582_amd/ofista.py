@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         "ofista_reset": (i32, [vp]),
         "ofista_push_pulse": (i32, [vp, vp, i32, f64]),
         "ofista_reconstruct": (i32, [vp, i32, vp]),
+        "ofista_reconstruct_static": (i32, [vp, i32, vp]),
         "ofista_image": (i32, [vp, vp]),
         "ofista_state": (i32, [vp, ctypes.POINTER(OfistaStats)]),
         "ofista_bp_image": (i32, [vp, vp]),
@@ -215,6 +216,15 @@ class OnlineFista:
         o = self._out(out, self.M) if copy else None
         self._check(self._lib.ofista_reconstruct(self._ctx, int(iters),
                                                  _ptr(o) if o is not None else None))
+        return o
+
+    def reconstruct_static(self, iters: int, out: torch.Tensor | None = None,
+                           copy: bool = True):
+        """reconstruct() with the matvec partials in the library's per-GPU static
+        array (the allocation-free entry point)."""
+        o = self._out(out, self.M) if copy else None
+        self._check(self._lib.ofista_reconstruct_static(self._ctx, int(iters),
+                                                        _ptr(o) if o is not None else None))
         return o
 
     def image(self, out=None):

@@ -93,6 +93,7 @@ def test_null_ctx_and_error_strings():
     assert L.ofista_reset(None) == -1
     assert L.ofista_push_pulse(None, None, 0, 0.0) == -1
     assert L.ofista_reconstruct(None, 1, None) == -1
+    assert L.ofista_reconstruct_static(None, 1, None) == -1
     L.ofista_destroy(None)
     for st in (0, -1, -2, -3, -4, -5, -6):
         assert L.ofista_error_string(None, st)
