@@ -75,6 +75,12 @@ enum { OFISTA_DICT_IDENTITY = 0, OFISTA_DICT_HAAR2D = 1, OFISTA_DICT_EDGELET = 2
    each operand (three products, FP32 accumulation; needs n_freq divisible by
    32, else OFISTA_E_UNSUPPORTED). */
 enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
+/* Workgroup layout of the split-BF16 Gram update (the same sums in the same
+   order, so H is bitwise the same): AUTO = BLOCK from 256 tile rows on, else
+   TILE; TILE = one 64 x 64 tile per workgroup (a 32 x 32 quadrant per wave);
+   BLOCK = 2 x 2 tiles per workgroup (a whole tile per wave).  Must be AUTO
+   with FP32 (else OFISTA_E_UNSUPPORTED). */
+enum { OFISTA_GRAM_AUTO = 0, OFISTA_GRAM_TILE = 1, OFISTA_GRAM_BLOCK = 2 };
 /* L_n rule (Section III-B asks for L >= ||sum G^H G||_2; Section III-C bounds
    its growth by ||G_n||_2^2 per pulse):
    RUNNING = rho + the sum of sigma^2 over the pulses pushed since the last
@@ -135,6 +141,7 @@ typedef struct ofista_config {
   int32_t backprojection;  /* != 0: push_pulse also accumulates the BP image
                               (see ofista_bp_image)                          */
   int32_t storage;         /* OFISTA_STORE_*                                   */
+  int32_t gram_layout;     /* OFISTA_GRAM_* (split-BF16 only)                  */
 } ofista_config;
 
 typedef struct ofista_stats {

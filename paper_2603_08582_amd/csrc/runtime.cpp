@@ -245,6 +245,12 @@ ofista_status check(const ofista_config *c, std::string *why) {
   if (c->momentum < OFISTA_MOMENTUM_FISTA || c->momentum > OFISTA_MOMENTUM_ISTA)
     return bad("unknown momentum mode");
   if (c->record_every < 0) return bad("record_every must be >= 0");
+  if (c->gram_layout < OFISTA_GRAM_AUTO || c->gram_layout > OFISTA_GRAM_BLOCK)
+    return bad("unknown gram_layout");
+  if (c->gram_layout != OFISTA_GRAM_AUTO && c->precision != OFISTA_PREC_SPLIT_BF16) {
+    if (why) *why = "gram_layout selects among the split-BF16 Gram kernels only";
+    return OFISTA_E_UNSUPPORTED;
+  }
   if (c->precision == OFISTA_PREC_SPLIT_BF16 && c->n_freq % 32 != 0) {
     if (why) *why = "split-BF16 Gram update needs n_freq divisible by 32";
     return OFISTA_E_UNSUPPORTED;
@@ -328,7 +334,9 @@ Layout layout(const ofista_config *c) {
     L.pix_atom = take(L.nnz * sizeof(int));
   }
   L.Ahi = L.Alo = 0;
-  if (c->precision == OFISTA_PREC_SPLIT_BF16 && L.nb >= kBfBlockMinNb) {
+  const bool bf_blocked = c->gram_layout == OFISTA_GRAM_BLOCK ||
+                          (c->gram_layout == OFISTA_GRAM_AUTO && L.nb >= kBfBlockMinNb);
+  if (c->precision == OFISTA_PREC_SPLIT_BF16 && bf_blocked) {
     const size_t nbB = (L.nb + 1) / 2;
     L.nbf_blocks = nbB * (nbB + 1) / 2;
     L.bf_blocks = take(L.nbf_blocks * sizeof(int2));
