@@ -55,45 +55,78 @@ def traffic_for(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, pulses: int, positions=None, diff: bool = False):
-    """The FP64 oracle as it stands, on the first `pulses` pulses (of
-    `positions` when given: the Bernoulli-selected ones of a session).  With
-    diff, the oracle's forward run plus its reverse pass for dL/dlambda and
-    dL/dphase over those pulses (the differentiation form's step)."""
-    from oracle import sar
-    from oracle.online_fista import OnlineFistaOracle
+def host_description():
+    """CPU model and the BLAS numpy is linked against (reported with the
+    oracle's baseline)."""
+    model = "unknown"
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name', '?')} {b.get('version', '')}".strip()
+    except Exception:
+        pass
+    return model, blas
+
+
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads", 1) for i in threadpool_info()
-                       if i.get("user_api") == "blas"), default=1)
+        return max((i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"), default=1)
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(wl, pulses: int, positions=None, diff: bool = False, runs: int = 5):
+    """The FP64 oracle as it stands, on the first `pulses` pulses (of
+    `positions` when given: the Bernoulli-selected ones of a session): one
+    untimed warm-up pulse, then `runs` timed runs from a fresh oracle, median
+    reported.  With diff, the oracle's forward run plus its reverse pass for
+    dL/dlambda and dL/dphase over those pulses (the differentiation form's
+    step)."""
+    from oracle import sar
+    from oracle.online_fista import OnlineFistaOracle
+    threads = blas_threads()
+    model, blas = host_description()
     order_all = list(range(wl.spec.n_pulses)) if positions is None else [int(p) for p in positions]
     order = order_all[:pulses]
     d = sar.echoes(wl, pulses=order)
-    o = OnlineFistaOracle.from_workload(wl)
     m = wl.spec.inner_steps
-    if diff:
-        from oracle import adjoint
-        o.push_pulse(d[0], 0)
-        lam = o.lam
-        t0 = time.perf_counter()
-        adjoint.gradients(wl, d, lam, np.zeros(len(order)), m, np.abs(wl.rho), pulses=len(order))
-        dt = time.perf_counter() - t0
-        return {"value": len(order) / dt, "unit": "pulses/s", "cores": int(threads),
-                "kind": "oracle",
-                "sample": f"first {len(order)} of the {len(order_all)} pulses of the same workload: "
-                          f"recorded forward ({m} FISTA steps per pulse) and the reverse pass for "
-                          f"dL/dlambda and dL/dphase, numpy complex128, {dt:.1f} s"}
-    t0 = time.perf_counter()
-    for p in order:
-        o.push_pulse(d[p], p)
-        o.reconstruct(m)
-    dt = time.perf_counter() - t0
-    pulses = len(order)
-    return {"value": pulses / dt, "unit": "pulses/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {pulses} of the {len(order_all)} pulses of the same workload "
-                      f"(push + {m} FISTA steps each), numpy complex128, {dt:.1f} s"}
+    warm = OnlineFistaOracle.from_workload(wl)
+    warm.push_pulse(d[order[0]], order[0])
+    warm.reconstruct(m)
+    times = []
+    for _ in range(runs):
+        o = OnlineFistaOracle.from_workload(wl)
+        if diff:
+            from oracle import adjoint
+            o.push_pulse(d[0], 0)
+            lam = o.lam
+            t0 = time.perf_counter()
+            adjoint.gradients(wl, d, lam, np.zeros(len(order)), m, np.abs(wl.rho),
+                              pulses=len(order))
+        else:
+            t0 = time.perf_counter()
+            for p in order:
+                o.push_pulse(d[p], p)
+                o.reconstruct(m)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    what = (f"recorded forward ({m} FISTA steps per pulse) and the reverse pass for "
+            f"dL/dlambda and dL/dphase" if diff else f"push + {m} FISTA steps each")
+    return {"value": len(order) / dt, "unit": "pulses/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {len(order)} of the {len(order_all)} pulses of the same workload "
+                      f"({what}), numpy complex128; one warm-up pulse, median of {runs} runs "
+                      f"of {dt:.2f} s (min {min(times):.2f}, max {max(times):.2f})",
+            "cpu_model": model, "blas": blas, "runs": runs}
 
 
 def main():
@@ -102,7 +135,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="haar64")
-    ap.add_argument("--cpu-pulses", type=int, default=12)
+    ap.add_argument("--cpu-pulses", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="BLAS threads of the oracle baseline (0: the library's default, all cores)")
@@ -214,25 +247,31 @@ def main():
     torch.cuda.synchronize()
     if diff_mode:  # the split covers the timed steps only (the first run loads code)
         diff_split.update(forward_ms=0.0, loss_ms=0.0, backward_ms=0.0, n=0)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    for _ in range(args.steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for k in range(args.steps):
         step()
-    t1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    step_ms_each = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     if diff_mode:
         diff_timed = dict(diff_split)
 
     # per-kernel durations: the same steps again with HIP events around every
-    # launch of the Gram update and of the FISTA step (library stream)
-    g.profile(True)
-    for _ in range(args.steps):
-        step()
-    gram_ms, gram_n = g.kernel_time("gram")
-    step_ms, step_n = g.kernel_time("step")
-    g.profile(False)
+    # launch of the Gram update and of the FISTA step (library stream).  Not
+    # under rocprofv3 counter collection: event-attached launches are the
+    # suspected trigger of a fault seen in such a pass.
+    under_counters = bool(os.environ.get("ROCPROF_COUNTER_COLLECTION"))
+    if not under_counters:
+        g.profile(True)
+        for _ in range(args.steps):
+            step()
+        gram_ms, gram_n = g.kernel_time("gram")
+        step_ms, step_n = g.kernel_time("step")
+        g.profile(False)
+    else:
+        gram_ms, gram_n, step_ms, step_n = float("nan"), 0, float("nan"), 0
     x = g.image()
     torch.cuda.synchronize()
     finite = bool(torch.isfinite(torch.view_as_real(x)).all().item())
@@ -242,28 +281,43 @@ def main():
     M = g.M                                     # coefficients (= N except for edgelets)
     gram_flops = 4.0 * K * M * (M + 1)          # Hermitian upper triangle, per pulse
     step_bytes = 4.0 * M * (M + 1)              # upper-triangle complex64 H, per FISTA step
+    # MFMA work the Gram kernels issue: every stored 64 x 64 tile (diagonal
+    # tiles whole) over all K frequencies
+    nbt = (M + 63) // 64
+    tile_macs = K * 64 * 64 * nbt * (nbt + 1) // 2
     if s.precision == "split_bf16":
-        # three BF16 products per FP32 product (hi*hi + hi*lo + lo*hi)
-        rl_gram = {"bound": "mfma", "achieved": 3 * gram_flops / (gram_avg * 1e-3) / 1e12,
+        # three BF16 products (hi*hi + hi*lo + lo*hi) of the four real products
+        # of each complex product: 12 real multiply-adds per complex one
+        issued = 2.0 * 12 * tile_macs
+        rl_gram = {"bound": "mfma", "achieved": issued / (gram_avg * 1e-3) / 1e12,
                    "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "bf16x3",
                    "traffic": None, "kernel": "k_gram_bf16x3", "avg_ms": gram_avg,
-                   "launches": gram_n}
-    else:
-        # the kernel forms each complex product from three real products
-        # (Gauss), so the matrix cores execute 3/4 of the algorithmic flops
-        rl_gram = {"bound": "mfma", "achieved": gram_flops / (gram_avg * 1e-3) / 1e12,
-                   "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "fp32",
-                   "traffic": traffic_for("gram", args.workload), "kernel": "k_gram_fp32", "avg_ms": gram_avg,
                    "launches": gram_n,
-                   "executed_frac": 0.75 * gram_flops / (gram_avg * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
-                   "form": "three real products per complex product; achieved counts the "
-                           "algorithmic 4KN(N+1) flops, executed_frac the 3KN(N+1) issued"}
+                   "algorithmic_tflops": gram_flops / (gram_avg * 1e-3) / 1e12,
+                   "form": "achieved and frac count the BF16 flops the matrix cores issue "
+                           "(12 real products per complex product over the stored tiles); "
+                           "algorithmic_tflops the 4KN(N+1) of the FP32 product"}
+    else:
+        # Gauss's form: three real products per complex product
+        issued = 2.0 * 3 * tile_macs
+        rl_gram = {"bound": "mfma", "achieved": issued / (gram_avg * 1e-3) / 1e12,
+                   "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "fp32",
+                   "traffic": traffic_for("gram", args.workload), "kernel": "k_gram_fp32",
+                   "avg_ms": gram_avg, "launches": gram_n,
+                   "algorithmic_tflops": gram_flops / (gram_avg * 1e-3) / 1e12,
+                   "form": "achieved and frac count the FP32 flops the matrix cores issue "
+                           "(three real products per complex product over the stored tiles); "
+                           "algorithmic_tflops the 4KN(N+1) of the complex product"}
     rl_step = {"bound": "hbm", "achieved": step_bytes / (step_avg * 1e-3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_for("step", args.workload),
                "kernel": "k_step_tiles", "avg_ms": step_avg, "launches": step_n}
     for r in (rl_gram, rl_step):
         r["frac"] = r["achieved"] / r["peak"]
-    dominant, other = (rl_step, rl_gram) if step_ms >= gram_ms else (rl_gram, rl_step)
+        if not np.isfinite(r["achieved"]):  # no per-kernel timing (counter collection)
+            for k in ("achieved", "frac", "avg_ms", "algorithmic_tflops"):
+                if k in r:
+                    r[k] = None
+    dominant, other = (rl_gram, rl_step) if gram_ms > step_ms else (rl_step, rl_gram)
 
     if s.dictionary == "edgelet":
         dict_desc = (f"edgelet(lengths {'/'.join(map(str, s.edge_lengths))}, rotations "
@@ -297,6 +351,8 @@ def main():
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
                    "parallelism": "single GPU"},
         "fista_iters_per_s": pulses_per_step[0] * m / (ms * 1e-3),
+        "median_ms_per_step": float(np.median(step_ms_each)),
+        "min_ms_per_step": float(np.min(step_ms_each)),
         "roofline": {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": dominant["kernel"],
         "roofline_other": other,
