@@ -142,6 +142,9 @@ typedef struct ofista_config {
                               (see ofista_bp_image)                          */
   int32_t storage;         /* OFISTA_STORE_*                                   */
   int32_t gram_layout;     /* OFISTA_GRAM_* (split-BF16 only)                  */
+  int32_t validate_input;  /* != 0: ofista_push_pulse checks every sample of
+                              d_s and returns OFISTA_E_ARG, changing nothing,
+                              if one is not finite (costs a stream sync)   */
 } ofista_config;
 
 typedef struct ofista_stats {
@@ -156,7 +159,10 @@ typedef struct ofista_stats {
   double sigma2;           /* ||A_s||_2^2 of the last pushed pulse            */
 } ofista_stats;
 
-/* Device bytes the workspace must have for cfg (H, b, coefficient and momentum
+/* Section III-D / Table I: the storage of Online FISTA is the sufficient
+   statistics (H: the M x M Gram, kept as its packed Hermitian upper triangle,
+   and b: M entries) plus the coefficients, independent of the pulse count.
+   Device bytes the workspace must have for cfg (H, b, coefficient and momentum
    vectors, power vector, matvec partials, one pulse's A_s, tables, the partial
    tiles of the FP32 Gram update's split remainder (at most 255 x 8 tiles of
    32 KB, 8 MB at N = 4096), and the
@@ -172,7 +178,10 @@ ofista_status ofista_check_config(const ofista_config *cfg);
    invalid.  Pure host function. */
 int64_t ofista_coef_count(const ofista_config *cfg);
 
-/* init(scene, geometry, lambda).  Validates cfg, carves the caller-owned
+/* init(scene, geometry, lambda): the problem of Section III-B (the weighted
+   LASSO over the coefficients of the dictionary of Section III-A, with the
+   forward model of Section II on the given grid, positions and frequencies)
+   before any pulse, H = 0 and b = 0 (Section III-C).  Validates cfg, carves the caller-owned
    workspace (device memory of at least ofista_workspace_bytes(cfg) bytes,
    256-byte aligned, kept alive by the caller until ofista_destroy), copies the
    host tables, precomputes ||A_s||_2^2 for every position (it depends only on
@@ -184,11 +193,15 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace,
                             size_t workspace_bytes, void *hip_stream,
                             struct ofista_ctx **out);
 
-/* Zero the online state (H, b, c, t, L, lambda, power vector, pulse count) so
-   that a new image can be formed with the same geometry tables. */
+/* Zero the online state (H, b, c, t, L, lambda, power vector, pulse count) --
+   the start of the Section III-C recursions, H_0 = 0 and b_0 = 0 -- so that a
+   new image can be formed with the same geometry tables. */
 ofista_status ofista_reset(struct ofista_ctx *ctx);
 
-/* push_pulse(d_s, s): one received pulse.  d_pulse: device, K complex64; s:
+/* push_pulse(d_s, s): one received pulse, Section III-C: the Delta-A / Delta-b
+   equations (H += A_s^H A_s, b += A_s^H d_s with R_n = I) folded into the
+   A_n / b_n recursions, and the step bound grown by ||A_s||_2^2 (the
+   incremental bound; see OFISTA_LIP_*).  d_pulse: device, K complex64; s:
    index of the platform position (0 <= s < n_pos; positions may repeat or be
    skipped).  The data used is d_s * exp(-i phase_corr).  Enqueues A_s, the H
    and b updates, lambda at the first pulse, and L_n, tau. */
@@ -237,7 +250,9 @@ ofista_status ofista_bp_image(struct ofista_ctx *ctx, void *d_img_out);
    (the count is returned on the host). */
 ofista_status ofista_count_large(struct ofista_ctx *ctx, double threshold, int64_t *count);
 
-/* Host copy of the scalar state.  Synchronises the stream. */
+/* Host copy of the scalar state: the pulse and step counts, the momentum
+   scalar t of Algorithm 1, L_n and tau = 1/L_n (Section III-B), lambda, and
+   the running spectral estimate.  Synchronises the stream. */
 ofista_status ofista_state(struct ofista_ctx *ctx, ofista_stats *out);
 
 /* Synthetic radar return for position s (the Section II measurement model):
@@ -264,9 +279,11 @@ ofista_status ofista_gram_entries(struct ofista_ctx *ctx, int32_t n, const int32
 ofista_status ofista_gram(struct ofista_ctx *ctx, void *d_out);
 ofista_status ofista_vector(struct ofista_ctx *ctx, int32_t which, void *d_out);
 
-/* Resumable state record (n, t, L, lambda, power vector, c_hat, b, H, and the
-   BP accumulator when enabled), so that
-   a run split at any pulse and resumed equals the uninterrupted run.  The
+/* Resumable state record: the sufficient statistics of Section III-C (H_n and
+   b_n carry everything the past pulses contribute, so resuming from them
+   equals the uninterrupted run) plus the iteration state of Algorithm 1
+   (n, t, L, lambda, power vector, c_hat) and the BP accumulator when
+   enabled.  The
    buffer is caller-owned device memory of ofista_state_bytes(cfg) bytes;
    alignment padding inside it is left unwritten.  Export synchronises the
    stream; import synchronises it and forgets any recorded history. */

@@ -25,7 +25,7 @@ LIB = HERE / "libofista.so"
 BUILD = HERE.parent / "_build" / "ofista"
 
 ARCH = os.environ.get("OFISTA_ARCH", "gfx950")
-SOURCES = ["rows.hip", "gram.hip", "fista.hip", "adjoint.hip", "runtime.cpp"]
+SOURCES = ["rows.hip", "gram.hip", "fista.hip", "adjoint.hip", "host_plan.cpp", "runtime.cpp"]
 # Per-source extra flags.  The Gram kernels keep their MFMA accumulators in
 # ordinary VGPRs (no copies to and from the accumulation registers around
 # each LDS stage): same results bit for bit, fewer registers, higher occupancy.

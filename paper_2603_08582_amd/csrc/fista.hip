@@ -459,7 +459,31 @@ __global__ void k_scale(const float2 *__restrict__ x, float scale, int n, float2
   if (i < n) out[i] = make_float2(x[i].x * scale, x[i].y * scale);
 }
 
+// Number of samples of a pulse with a non-finite component (input validation):
+// one workgroup, integer sum.
+__global__ __launch_bounds__(256) void k_count_nonfinite(const float2 *__restrict__ d, int K,
+                                                         unsigned *__restrict__ count) {
+  unsigned n = 0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const float2 v = d[k];
+    n += (isfinite(v.x) && isfinite(v.y)) ? 0u : 1u;
+  }
+  __shared__ unsigned red[256];
+  red[threadIdx.x] = n;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = red[0];
+}
+
 }  // namespace
+
+hipError_t launch_count_nonfinite(const float2 *d, int K, unsigned *count, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(256), 0, st, d, K, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_count_large(const float2 *c, int M, float thr, unsigned *count, hipStream_t st) {
   int blocks = (M + 255) / 256;

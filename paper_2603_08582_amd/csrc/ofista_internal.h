@@ -8,17 +8,18 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "host_plan.h"
+
 namespace ofista {
+
+static_assert(sizeof(float2) == kBytesC64 && sizeof(float4) == kBytesF4 &&
+                  sizeof(double2) == kBytesD2 && sizeof(int2) == kBytesI2,
+              "layout byte sizes");
 
 // Vector types for nontemporal loads (the builtin takes scalar or
 // ext_vector_type pointers only).
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// Edge of the square tiles of the packed Hermitian storage.  H is kept as
-// the nb(nb+1)/2 tiles (I, J), I <= J, of a zero-padded Npad x Npad matrix
-// (Npad = nb * kTile), each tile row-major, tiles in row-major upper order.
-constexpr int kTile = 64;
 
 // Slot of the matvec partials (nb x nb slots of kTile float4) that holds the
 // contribution of source tile row/column v to target tile row R.  Row partials
@@ -30,33 +31,8 @@ __host__ __device__ inline size_t slot_index(int v, int R, int nb) {
   return v >= R ? static_cast<size_t>(R) * nb + v
                 : static_cast<size_t>(nb - 1 - v) * nb + (nb - 1 - R);
 }
-// Tiles per FISTA work item (a run of tiles along one tile row): 2 or 4.
-constexpr int kChunk = 2;
-// Workgroups per tile row in the FISTA update; the power-iteration parts
-// (slots) are kept per update workgroup: nparts = kUpdSplit * nb.
-constexpr int kUpdSplit = 2;
-// Frequencies staged per LDS step of the Gram update.
-constexpr int kGramKB = 16;
-
-// Largest number of frequencies per pulse.
-constexpr int kMaxFreq = 1024;
-
 constexpr double kC0 = 299792458.0;  // speed of light, m/s
 constexpr double kPi = 3.141592653589793238462643383279502884;
-
-// Scalars that live on the device because they depend on data.
-struct DevScalars {
-  double lam;           // l1 weight
-  double L;             // L_n
-  double tau;           // 1 / L_n
-  double alpha;         // lam * tau, the shrink threshold
-  double sigma2;        // ||A_s||_2^2 of the last pushed pulse
-  double rho;           // Rayleigh quotient of the last FISTA step before the last push
-  unsigned dbmax_bits;  // max_i |Delta b_i| of the first pulse, float bits
-  unsigned pad0;
-  double sig2_acc;      // sum of sigma^2 of the pulses pushed since that step
-  double pad1;
-};
 
 // Geometry passed by value.  N is the coefficient count M (the length of b,
 // c and every FISTA vector; Npad = M rounded up to kTile), npix = nx*ny the
@@ -78,11 +54,6 @@ struct DictTabs {
   const int *atom_pix;
   const int *pix_ptr;    // npix + 1 offsets into pix_atom
   const int *pix_atom;
-};
-
-// One FISTA work item: tile row I, tiles J0 .. J1-1 (J0 >= I).
-struct WorkItem {
-  int I, J0, J1, pad;
 };
 
 // Device-side pointers of one context, carved from the workspace.
@@ -219,7 +190,6 @@ hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0 =
 // the stacked operator (rows x Npad, M used); P[c][m] = sum over rows
 // r in [64c, 64c + 64) of conj(G[r, m]) U[r]; then launch_step_update with
 // P set.  D: rows complex64 (the rotated data).
-constexpr int kStoreRows = 64;
 hipError_t launch_store_forward(const float2 *G, const float2 *D, int rows, int Npad, int M,
                                 const float2 *z, const float2 *w, float4 *U, hipStream_t st,
                                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
@@ -235,6 +205,8 @@ hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
 // *count (zeroed by the caller) += #{m < M : |c_m| > thr} (FP32 magnitude).
 hipError_t launch_count_large(const float2 *c, int M, float thr, unsigned *count, hipStream_t st);
+// *count = number of the K samples of d with a non-finite component.
+hipError_t launch_count_nonfinite(const float2 *d, int K, unsigned *count, hipStream_t st);
 // out[i] = x[i] * scale for i < n.
 hipError_t launch_scale(const float2 *x, float scale, int n, float2 *out, hipStream_t st);
 hipError_t launch_init_power(float2 *w, double *slot0, double *slot1, int N,

@@ -53,7 +53,7 @@ class OfistaConfig(ctypes.Structure):
         ("n_edge_rotations", ctypes.c_int32),
         ("edge_rotations_deg", ctypes.POINTER(ctypes.c_double)),
         ("backprojection", ctypes.c_int32), ("storage", ctypes.c_int32),
-        ("gram_layout", ctypes.c_int32),
+        ("gram_layout", ctypes.c_int32), ("validate_input", ctypes.c_int32),
     ]
 
 
@@ -116,7 +116,8 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
                 dictionary="identity", haar_levels=0, lam=0.05, lam_relative=True,
                 precision="fp32", lipschitz="running", momentum="fista",
                 record_every=0, max_pulses=0, max_iters=0, edge_lengths=(), edge_rotations=(),
-                backprojection=False, storage="gram", gram_layout="auto"):
+                backprojection=False, storage="gram", gram_layout="auto",
+                validate_input=False):
     """Build an OfistaConfig; returns (config, keepalive) -- keep the second
     value alive while the config is in use (it owns the host tables)."""
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
@@ -134,7 +135,7 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
         n_edge_rotations=rots.size,
         edge_rotations_deg=rots.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         backprojection=1 if backprojection else 0, storage=STORAGE[storage],
-        gram_layout=GRAM_LAYOUT[gram_layout])
+        gram_layout=GRAM_LAYOUT[gram_layout], validate_input=1 if validate_input else 0)
     return cfg, (pos, lens, rots)
 
 

@@ -260,3 +260,29 @@ def test_errors_are_reported():
     g.push_pulse(d[0], 0)
     g.reconstruct(0)
     assert g.state()["n_pulses"] == 1
+
+
+def test_validation_rejects_non_finite_pulses():
+    """With validate_input, a pulse holding NaN or inf is refused with E_ARG and
+    leaves the state untouched; the run then continues as if it never came."""
+    from paper_2603_08582_amd import OfistaError
+    wl = make_workload(tiny_spec(n_pulses=3))
+    d = echoes64(wl)
+    g = make_gpu(wl, validate_input=True)
+    ref = make_gpu(wl)
+    dd = dev(d)
+    g.push_pulse(dd[0], 0)
+    for bad_value in (np.nan, np.inf):
+        bad = d[1].copy()
+        bad[7] = complex(0.0, bad_value)
+        with pytest.raises(OfistaError) as e:
+            g.push_pulse(dev(bad), 1)
+        assert e.value.status == -1 and "non-finite" in str(e.value)
+        assert g.state()["n_pulses"] == 1
+    ref.push_pulse(dd[0], 0)
+    for p in (1, 2):
+        g.push_pulse(dd[p], p)
+        ref.push_pulse(dd[p], p)
+    g.reconstruct(20, copy=False)
+    ref.reconstruct(20, copy=False)
+    assert np.array_equal(host(g.vector("c")), host(ref.vector("c")))
