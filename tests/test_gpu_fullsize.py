@@ -4,10 +4,14 @@
   bench.py runs it, against the oracle's stored result (written by
   tests/golden/make_golden.py, which calls only the oracle): final image
   within the FP32 image tolerance 1e-4, every L_n and lambda within 1e-6.
-* large (128x128 pixels, K=512, 256 pulses, m=20): the full oracle run is too
-  slow for a test, so the oracle computes sampled entries one by one --
-  H_n[i, j] and b_n[i] as direct FP64 sums over pulses and frequencies,
-  sigma^2 of sample positions, and lambda from the first pulse.
+* large (128x128 pixels, K=512, 256 pulses, m=20, 200 scatterers over a
+  40 dB range) against the oracle's stored result (tests/golden/
+  large_oracle.npz, same script): the image within 1e-4 relative L2 and
+  element by element within 1e-3 of max |x|, the support of c outside a band
+  of 1e-3 max |c| on both sides, every L_n and lambda within 1e-6; plus
+  sampled entries the oracle computes one by one -- H_n[i, j] and b_n[i] as
+  direct FP64 sums over pulses and frequencies, sigma^2 of sample positions,
+  and lambda from the first pulse.
 """
 
 from pathlib import Path
@@ -71,7 +75,7 @@ def direct_b_entry(wl, pix, d, i, pulses):
     return tot
 
 
-def test_large_full_run_sampled_entries():
+def test_large_full_run_against_oracle():
     from paper_2603_08582_amd import OnlineFista
     wl = make_workload("large")
     s = wl.spec
@@ -79,14 +83,37 @@ def test_large_full_run_sampled_entries():
     d = sar.echoes(wl).astype(np.complex64)
     g = OnlineFista(**library_kwargs(wl))
     dd = torch.from_numpy(d).cuda()
-    lam = None
+    Ls, lams = [], []
     for p in range(P):
         g.push_pulse(dd[p], p)
-        if p == 0:
-            lam = g.state()["lam"]
+        st = g.state()
+        Ls.append(st["L"])
+        lams.append(st["lam"])
         g.reconstruct(s.inner_steps, copy=False)
+    lam = lams[0]
     st = g.state()
     assert st["n_pulses"] == P and st["n_iters"] == P * s.inner_steps
+    # the whole run against the oracle's stored result
+    ref = np.load(GOLDEN / "large_oracle.npz")
+    assert np.max(np.abs(np.array(Ls) / ref["L"] - 1)) < 1e-6
+    assert np.max(np.abs(np.array(lams) / ref["lam"] - 1)) < 1e-6
+    assert abs(st["t"] - float(ref["t"])) < 1e-9 * float(ref["t"])
+    x = g.image().cpu().numpy().astype(np.complex128)
+    xo = ref["image"]
+    err = rel(x, xo)
+    emax = float(np.max(np.abs(x - xo)) / np.max(np.abs(xo)))
+    c = g.vector("c").cpu().numpy().astype(np.complex128)
+    co = ref["c"]
+    band = 1e-3 * np.max(np.abs(co))
+    sup = wl.support
+    found_o = int(np.count_nonzero(np.abs(co[sup]) > band))
+    found_g = int(np.count_nonzero(np.abs(c[sup]) > band))
+    print(f"large full run: image rel {err:.3e}, max element {emax:.3e}; scatterer pixels "
+          f"above the band: oracle {found_o}, GPU {found_g} of {len(sup)}")
+    assert err < 1e-4 and emax < 1e-3
+    # support outside the band: what one side holds above it, the other holds too
+    assert np.all(c[np.abs(co) > band] != 0)
+    assert np.all(co[np.abs(c) > band] != 0)
     pix = wl.pixel_xyz()
     d64 = d.astype(np.complex128)
     # lambda from the first pulse
@@ -120,9 +147,4 @@ def test_large_full_run_sampled_entries():
         # FP64 on both sides; the oracle's F F^H carries ~4e-10 relative
         # rounding from its ~4e6 rad phases
         assert abs(g.state()["sigma2"] / ref - 1) < 3e-9
-    x = g.image().cpu().numpy()
-    assert np.all(np.isfinite(x))
-    # the strongest scatterers are found
-    strongest = wl.support[np.argsort(-np.abs(wl.rho[wl.support]))[:20]]
-    top = set(np.argsort(-np.abs(x))[:100].tolist())
-    assert len(top.intersection(strongest.tolist())) >= 15
+    assert np.all(np.isfinite(g.image().cpu().numpy()))
