@@ -22,9 +22,9 @@ constexpr int kTile = 64;
 constexpr int kChunk = 2;
 // Workgroups per tile row in the FISTA update; the power-iteration parts
 // (slots) are kept per update workgroup: nparts = kUpdSplit * nb.
-constexpr int kUpdSplit = 2;
+constexpr int kUpdSplit = 4;
 // Frequencies staged per LDS step of the Gram update.
-constexpr int kGramKB = 16;
+constexpr int kGramKB = 32;
 
 // Largest number of frequencies per pulse.
 constexpr int kMaxFreq = 1024;
