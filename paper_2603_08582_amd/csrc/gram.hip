@@ -325,13 +325,21 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, const float2 *__restrict__
 // ---------------------------------------------------------------------------
 // Precision form: split-BF16 Gram update.  Each FP32 component x of A_s is
 // split once per pulse into hi = bf16(x) and lo = bf16(x - hi) (round to
-// nearest even), stored pixel-major so that one 16-byte read gives a lane the
-// (re, im) pairs of 4 consecutive frequencies.  Per 8 frequencies a wave
-// issues v_mfma_f32_32x32x16_bf16 three times per plane (hi*hi + hi*lo +
-// lo*hi, the lo*lo term dropped) accumulating in FP32: Re uses B = (ar', ai')
-// and Im uses B = (ai', -ar'), as in the FP32 kernel.  A and B fragments use
-// the same lane/element-to-k assignment, so every (frequency, component)
-// pair is contracted with its own partner whatever that assignment is.
+// nearest even).  Per 8 frequencies a wave issues v_mfma_f32_32x32x16_bf16
+// three times per plane (hi*hi + hi*lo + lo*hi, the lo*lo term dropped)
+// accumulating in FP32: Re uses B = (ar', ai') and Im uses B = (ai', -ar'), as
+// in the FP32 kernel.  A and B fragments use the same lane/element-to-k
+// assignment, so every (frequency, component) pair is contracted with its own
+// partner whatever that assignment is.
+//
+// Plane layout (hi and lo alike): a word holds one frequency's (re, im) bf16
+// pair, re in the low half.  The words are grouped in panel-stage blocks of
+// 4 KB, one per 64-pixel panel P and stage s of 16 frequencies, at word
+// (P * K/16 + s) * 1024; inside a block, the 16-byte chunk 64 fq + c holds the
+// four frequencies 16 s + 4 fq .. +3 of pixel 64 P + c.  A lane's MFMA
+// fragment (one pixel, four frequencies) is one chunk, a block is staged into
+// LDS as it is, and 16 consecutive lanes read 16 consecutive chunks, so the
+// LDS reads are free of bank conflicts.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -343,9 +351,11 @@ __device__ __forceinline__ unsigned bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_float(unsigned h) { return __uint_as_float(h << 16); }
 
 constexpr int kSplitTile = 64;
+constexpr int kPanelStage = 16;                   // frequencies per panel-stage block
+constexpr int kBlockWords = kTile * kPanelStage;  // 1024 words = 4 KB
 
-// A (K x Npad complex64, frequency rows) -> Ahi, Alo (Npad x K words, word =
-// re in the low half, im in the high half).  64 x 64 transpose through LDS.
+// A (K x Npad complex64, frequency rows) -> Ahi, Alo in panel-stage blocks.
+// One workgroup per 64 pixels x 64 frequencies, transposed through LDS.
 __global__ __launch_bounds__(256) void k_split_bf16(int K, int Npad, const float2 *__restrict__ A,
                                                     unsigned *__restrict__ Ahi,
                                                     unsigned *__restrict__ Alo) {
@@ -358,23 +368,31 @@ __global__ __launch_bounds__(256) void k_split_bf16(int K, int Npad, const float
     tile[f][px] = k0 + f < K ? A[static_cast<size_t>(k0 + f) * Npad + p0 + px] : make_float2(0.f, 0.f);
   }
   __syncthreads();
+  const size_t nS = static_cast<size_t>(K) / kPanelStage;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < 4; ++r) {
     const int idx = threadIdx.x + 256 * r;
-    const int px = idx >> 6, f = idx & 63;
-    if (k0 + f < K) {
-      const float2 v = tile[f][px];
-      const unsigned hr = bf16_rne(v.x), hi = bf16_rne(v.y);
-      const unsigned lr = bf16_rne(v.x - bf16_to_float(hr)), li = bf16_rne(v.y - bf16_to_float(hi));
-      const size_t o = static_cast<size_t>(p0 + px) * K + k0 + f;
-      Ahi[o] = hr | (hi << 16);
-      Alo[o] = lr | (li << 16);
+    const int c = idx & 63, quad = idx >> 6;  // quad: 4 frequencies 4 quad .. +3 of the tile
+    const int k = k0 + 4 * quad;
+    if (k < K) {  // K is a multiple of 16: a chunk is all in or all out
+      unsigned hw[4], lw[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const float2 v = tile[4 * quad + w][c];
+        const unsigned hr = bf16_rne(v.x), hi = bf16_rne(v.y);
+        const unsigned lr = bf16_rne(v.x - bf16_to_float(hr)), li = bf16_rne(v.y - bf16_to_float(hi));
+        hw[w] = hr | (hi << 16);
+        lw[w] = lr | (li << 16);
+      }
+      const size_t chunk = ((blockIdx.x * nS + (k >> 4)) * 4 + ((k >> 2) & 3)) * kTile + c;
+      typedef unsigned u4 __attribute__((ext_vector_type(4)));
+      reinterpret_cast<u4 *>(Ahi)[chunk] = u4{hw[0], hw[1], hw[2], hw[3]};
+      reinterpret_cast<u4 *>(Alo)[chunk] = u4{lw[0], lw[1], lw[2], lw[3]};
     }
   }
 }
 
-constexpr int kBfKB = 32;             // frequencies per LDS stage
-constexpr int kBfStride = kBfKB + 4;  // words per column in LDS (padding against bank conflicts)
+constexpr int kBfKB = 32;  // frequencies per LDS stage of the one-tile kernel (two blocks)
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -385,13 +403,17 @@ __device__ __forceinline__ u32x4 im_operand(u32x4 v) {
   return (v >> 16u) | ((v ^ 0x8000u) << 16u);
 }
 
+// One 64 x 64 tile per workgroup, 4 waves each owning a 32 x 32 quadrant; a
+// stage (two panel-stage blocks per plane and side) is loaded into registers
+// while the matrix cores work on the previous one.  Launch order as in the
+// FP32 kernel (contiguous runs of the tile table per XCD).
 __global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles_grid,
                                                      const unsigned *__restrict__ Ahi,
                                                      const unsigned *__restrict__ Alo,
                                                      const int2 *__restrict__ tile_ij,
                                                      float2 *__restrict__ H) {
-  __shared__ unsigned sAh[kTile * kBfStride], sAl[kTile * kBfStride];
-  __shared__ unsigned sBh[kTile * kBfStride], sBl[kTile * kBfStride];
+  constexpr int kStageChunks = 2 * kBlockWords / 4;  // 512 chunks per plane and side
+  __shared__ u32x4 sAh[kStageChunks], sAl[kStageChunks], sBh[kStageChunks], sBl[kStageChunks];
   const int per = ntiles_grid >> 3;
   const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int2 ij = tile_ij[logical];
@@ -407,53 +429,47 @@ __global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles
     accR[r] = 0.f;
     accI[r] = 0.f;
   }
-  // staging: per plane and operand 64 columns x 32 frequencies = 512 uint4;
-  // element r of a thread is column (t + 256 r) / 8, frequencies
-  // 4 ((t + 256 r) % 8) .. +3 of the stage
+  // a stage is 2 consecutive blocks = 512 consecutive chunks per plane and
+  // side; thread t moves chunks t and t + 256
   const u32x4 *gAh = reinterpret_cast<const u32x4 *>(Ahi);
   const u32x4 *gAl = reinterpret_cast<const u32x4 *>(Alo);
-  const int Kq = K >> 2;  // uint4 per column
-  const int col0 = threadIdx.x >> 3, f40 = threadIdx.x & 7;
+  const size_t nS = static_cast<size_t>(K) / kPanelStage;
+  const size_t baseI = static_cast<size_t>(I) * nS * (kBlockWords / 4) + threadIdx.x;
+  const size_t baseJ = static_cast<size_t>(J) * nS * (kBlockWords / 4) + threadIdx.x;
   u32x4 pah[2], pal[2], pbh[2], pbl[2];
+  auto fetch = [&](int k0) {
+    const size_t o = static_cast<size_t>(k0 >> 4) * (kBlockWords / 4);
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const size_t oI = static_cast<size_t>(I * kTile + col0 + 32 * r) * Kq + f40;
-    const size_t oJ = static_cast<size_t>(J * kTile + col0 + 32 * r) * Kq + f40;
-    pah[r] = gAh[oI];
-    pal[r] = gAl[oI];
-    pbh[r] = gAh[oJ];
-    pbl[r] = gAl[oJ];
-  }
+    for (int r = 0; r < 2; ++r) {
+      pah[r] = gAh[baseI + o + 256 * r];
+      pal[r] = gAl[baseI + o + 256 * r];
+      pbh[r] = gAh[baseJ + o + 256 * r];
+      pbl[r] = gAl[baseJ + o + 256 * r];
+    }
+  };
+  auto stash = [&]() {
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int o = (col0 + 32 * r) * kBfStride + 4 * f40;
-    *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
-    *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
-    *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
-    *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
-  }
+    for (int r = 0; r < 2; ++r) {
+      sAh[threadIdx.x + 256 * r] = pah[r];
+      sAl[threadIdx.x + 256 * r] = pal[r];
+      sBh[threadIdx.x + 256 * r] = pbh[r];
+      sBl[threadIdx.x + 256 * r] = pbl[r];
+    }
+  };
+  fetch(0);
+  stash();
   __syncthreads();
   for (int k0 = 0; k0 < K; k0 += kBfKB) {
     const bool more = k0 + kBfKB < K;
-    if (more) {
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const size_t oI = static_cast<size_t>(I * kTile + col0 + 32 * r) * Kq + ((k0 + kBfKB) >> 2) + f40;
-        const size_t oJ = static_cast<size_t>(J * kTile + col0 + 32 * r) * Kq + ((k0 + kBfKB) >> 2) + f40;
-        pah[r] = gAh[oI];
-        pal[r] = gAl[oI];
-        pbh[r] = gAh[oJ];
-        pbl[r] = gAl[oJ];
-      }
-    }
+    if (more) fetch(k0 + kBfKB);
 #pragma unroll
     for (int g = 0; g < kBfKB / 8; ++g) {
-      const int oa = (wi * 32 + li) * kBfStride + 8 * g + 4 * h;
-      const int ob = (wj * 32 + li) * kBfStride + 8 * g + 4 * h;
-      const u32x4 ah = *reinterpret_cast<const u32x4 *>(&sAh[oa]);
-      const u32x4 al = *reinterpret_cast<const u32x4 *>(&sAl[oa]);
-      const u32x4 bh = *reinterpret_cast<const u32x4 *>(&sBh[ob]);
-      const u32x4 bl = *reinterpret_cast<const u32x4 *>(&sBl[ob]);
+      // frequencies 8 g + 4 h .. +3: block g / 2, quad 2 (g % 2) + h
+      const int q = (g >> 1) * 256 + (2 * (g & 1) + h) * 64;
+      const u32x4 ah = sAh[q + wi * 32 + li];
+      const u32x4 al = sAl[q + wi * 32 + li];
+      const u32x4 bh = sBh[q + wj * 32 + li];
+      const u32x4 bl = sBl[q + wj * 32 + li];
       const bf16x8 Ah = as_bf16x8(ah), Al = as_bf16x8(al);
       const bf16x8 Bh = as_bf16x8(bh), Bl = as_bf16x8(bl);
       const bf16x8 Bhi = as_bf16x8(im_operand(bh)), Bli = as_bf16x8(im_operand(bl));
@@ -466,14 +482,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles
     }
     __syncthreads();
     if (more) {
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const int o = (col0 + 32 * r) * kBfStride + 4 * f40;
-        *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
-        *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
-        *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
-        *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
-      }
+      stash();
       __syncthreads();
     }
   }
@@ -499,18 +508,45 @@ __global__ __launch_bounds__(256) void k_gram_bf16x3(int K, int Npad, int ntiles
 
 // Split-BF16 Gram over 2 x 2 blocks of tiles: wave w owns the whole 64 x 64
 // tile (I0 + w/2, J0 + w%2) as 2 x 2 quadrants, so every A fragment read from
-// LDS feeds two quadrants and every B fragment two: half the LDS reads per
-// MFMA of the one-quadrant-per-wave layout.
-constexpr int kBbKB = 16;              // frequencies per stage
-constexpr int kBbStride = kBbKB + 4;   // words per column in LDS
-__global__ __launch_bounds__(256) void k_gram_bf16_blk(int K, int Npad, int nbB,
-                                                       const unsigned *__restrict__ Ahi,
-                                                       const unsigned *__restrict__ Alo,
-                                                       const int2 *__restrict__ blocks,
-                                                       float2 *__restrict__ H) {
-  __shared__ unsigned sAh[2 * kTile * kBbStride], sAl[2 * kTile * kBbStride];
-  __shared__ unsigned sBh[2 * kTile * kBbStride], sBl[2 * kTile * kBbStride];
+// LDS feeds two quadrants and every B fragment two.  A stage is 8 frequencies:
+// one half panel-stage block (2 KB) per plane and panel, 8 of them (16 KB),
+// moved by direct global-to-LDS loads (global_load_lds_dwordx4: each lane's
+// 16 bytes land at the wave's LDS base + 16 lane) into a ring of RING LDS
+// buffers, RING - 1 stages ahead of the matrix cores.  No staging registers
+// are needed, so two workgroups (two waves per SIMD) fit on a CU.
+//
+// Per stage: wait until the own loads of this stage have landed (the newer
+// stages' loads stay in flight: vmcnt counts the loads in issue order), a
+// plain s_barrier (every wave's loads for the stage have landed, and every
+// wave has finished reading the buffer the next loads overwrite), read the
+// stage's fragments into registers, issue the loads of stage + RING - 1 into
+// the buffer read one stage earlier, then run the 24 MFMAs.  __syncthreads()
+// is not used: its release fence waits for all loads in flight, which would
+// cut the ring to one stage.  The MFMA sequence is the one of the one-tile
+// kernel per quadrant, so both layouts give the same H bit for bit.
+//
+// Block b of the launch takes table entry b; the host orders the table so
+// that XCD b % 8 gets a contiguous run of 8 x 8 super-blocks (blocks that
+// share panels run on one XCD).
+typedef __attribute__((address_space(1))) const void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+
+constexpr int kBbRing = 5;         // LDS buffers per workgroup (16 KB each)
+constexpr int kBbStageFreq = 8;    // frequencies per stage
+constexpr int kBbLoads = 4;        // global_load_lds_dwordx4 per wave per stage
+
+template <int RING>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_gram_bf16_blk(int K, int Npad, const unsigned *__restrict__ Ahi,
+                     const unsigned *__restrict__ Alo, const int2 *__restrict__ blocks,
+                     float2 *__restrict__ H) {
+  constexpr int kSlots = 8;  // [A hi t0, A hi t1, A lo t0, A lo t1, B hi t0, B hi t1, B lo t0, B lo t1]
+  constexpr int kSlotChunks = kBlockWords / 8;  // half a block: 128 chunks = 2 KB
+  constexpr int kBufChunks = kSlots * kSlotChunks;
+  static_assert(RING >= 2 && RING * kBufChunks * 16 <= 80 * 1024, "two workgroups per CU");
+  __shared__ u32x4 sbuf[RING * kBufChunks];
   const int2 blk = blocks[blockIdx.x];
+  if (blk.x < 0) return;
   const int IB = blk.x, JB = blk.y;
   const int nb = Npad / kTile;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -528,79 +564,73 @@ __global__ __launch_bounds__(256) void k_gram_bf16_blk(int K, int Npad, int nbB,
         acc[a][b][0][r] = 0.f;
         acc[a][b][1][r] = 0.f;
       }
-  // staging: per plane 128 columns x 16 frequencies = 512 u32x4; thread t
-  // loads columns (t >> 2) and (t >> 2) + 64, frequency quad t & 3
-  const u32x4 *gAh = reinterpret_cast<const u32x4 *>(Ahi);
-  const u32x4 *gAl = reinterpret_cast<const u32x4 *>(Alo);
-  const int Kq = K >> 2;
-  const int c0 = threadIdx.x >> 2, fq = threadIdx.x & 3;
-  auto colA = [&](int r) { return min(2 * IB * kTile + c0 + 64 * r, Npad - 1); };
-  auto colB = [&](int r) { return min(2 * JB * kTile + c0 + 64 * r, Npad - 1); };
-  u32x4 pah[2], pal[2], pbh[2], pbl[2];
-  auto fetch = [&](int k0) {
+  // wave w loads slots 2w and 2w + 1: side w / 2, plane w % 2, panels t = 0, 1
+  // (the last panel stands in for a missing one of a partial block).  Stage u
+  // of panel P is half u % 2 of block (P, u / 2): 512 words at
+  // (P K/16 + u/2) 1024 + (u % 2) 512.
+  const int nT = K / kBbStageFreq;
+  const unsigned *plane = (wave & 1) ? Alo : Ahi;
+  const int P0 = 2 * ((wave >> 1) ? JB : IB);
+  const unsigned *src[2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const size_t oA = static_cast<size_t>(colA(r)) * Kq + (k0 >> 2) + fq;
-      const size_t oB = static_cast<size_t>(colB(r)) * Kq + (k0 >> 2) + fq;
-      pah[r] = gAh[oA];
-      pal[r] = gAl[oA];
-      pbh[r] = gAh[oB];
-      pbl[r] = gAl[oB];
-    }
-  };
-  auto stash = [&]() {
+  for (int t = 0; t < 2; ++t)
+    src[t] = plane + static_cast<size_t>(min(P0 + t, nb - 1)) * (K / kPanelStage) * kBlockWords +
+             4 * lane;
+  auto load_stage = [&](int u, int buf) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int o = (c0 + 64 * r) * kBbStride + 4 * fq;
-      *reinterpret_cast<u32x4 *>(&sAh[o]) = pah[r];
-      *reinterpret_cast<u32x4 *>(&sAl[o]) = pal[r];
-      *reinterpret_cast<u32x4 *>(&sBh[o]) = pbh[r];
-      *reinterpret_cast<u32x4 *>(&sBl[o]) = pbl[r];
-    }
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        __builtin_amdgcn_global_load_lds(
+            (gptr_t)(src[t] + static_cast<size_t>(u) * (kBlockWords / 2) + 256 * j),
+            (lptr_t)(&sbuf[buf * kBufChunks + (2 * wave + t) * kSlotChunks + 64 * j]), 16, 0, 0);
   };
-  fetch(0);
-  stash();
-  __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += kBbKB) {
-    const bool more = k0 + kBbKB < K;
-    if (more) fetch(k0 + kBbKB);
+  for (int u = 0; u < RING - 1 && u < nT; ++u) load_stage(u, u);
+  int rb = 0, wb = RING - 1;  // buffer read at this stage, buffer loaded at this stage
+  for (int u = 0; u < nT; ++u) {
+    // the loads of stages u + 1 .. u + RING - 2 may stay in flight
+    if (nT - 1 - u >= RING - 2)
+      __asm__ volatile("s_waitcnt vmcnt(%0)" ::"n"((RING - 2) * kBbLoads) : "memory");
+    else
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+    const u32x4 *sb = &sbuf[rb * kBufChunks];
+    u32x4 ah[2], al[2], bh[2], bl[2];
     if (live) {
 #pragma unroll
-      for (int g = 0; g < kBbKB / 8; ++g) {
-        bf16x8 Ah[2], Al[2], Bh[2], Bl[2], Bhi[2], Bli[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int oa = (ti * kTile + 32 * q + li) * kBbStride + 8 * g + 4 * h;
-          const int ob = (tj * kTile + 32 * q + li) * kBbStride + 8 * g + 4 * h;
-          const u32x4 ah = *reinterpret_cast<const u32x4 *>(&sAh[oa]);
-          const u32x4 al = *reinterpret_cast<const u32x4 *>(&sAl[oa]);
-          const u32x4 bh = *reinterpret_cast<const u32x4 *>(&sBh[ob]);
-          const u32x4 bl = *reinterpret_cast<const u32x4 *>(&sBl[ob]);
-          Ah[q] = as_bf16x8(ah);
-          Al[q] = as_bf16x8(al);
-          Bh[q] = as_bf16x8(bh);
-          Bl[q] = as_bf16x8(bl);
-          Bhi[q] = as_bf16x8(im_operand(bh));
-          Bli[q] = as_bf16x8(im_operand(bl));
-        }
-#pragma unroll
-        for (int qi = 0; qi < 2; ++qi)
-#pragma unroll
-          for (int qj = 0; qj < 2; ++qj) {
-            floatx16 &R = acc[qi][qj][0], &Im = acc[qi][qj][1];
-            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bh[qj], R, 0, 0, 0);
-            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bhi[qj], Im, 0, 0, 0);
-            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bl[qj], R, 0, 0, 0);
-            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[qi], Bli[qj], Im, 0, 0, 0);
-            R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[qi], Bh[qj], R, 0, 0, 0);
-            Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[qi], Bhi[qj], Im, 0, 0, 0);
-          }
+      for (int q = 0; q < 2; ++q) {
+        const int c = h * 64 + 32 * q + li;
+        ah[q] = sb[(0 + ti) * kSlotChunks + c];
+        al[q] = sb[(2 + ti) * kSlotChunks + c];
+        bh[q] = sb[(4 + tj) * kSlotChunks + c];
+        bl[q] = sb[(6 + tj) * kSlotChunks + c];
       }
     }
-    __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
+    if (u + RING - 1 < nT) load_stage(u + RING - 1, wb);
+    rb = rb == RING - 1 ? 0 : rb + 1;
+    wb = wb == RING - 1 ? 0 : wb + 1;
+    if (live) {
+      bf16x8 Bhi[2], Bli[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        Bhi[q] = as_bf16x8(im_operand(bh[q]));
+        Bli[q] = as_bf16x8(im_operand(bl[q]));
+      }
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj) {
+          floatx16 &R = acc[qi][qj][0], &Im = acc[qi][qj][1];
+          const bf16x8 Ah = as_bf16x8(ah[qi]), Al = as_bf16x8(al[qi]);
+          const bf16x8 Bh = as_bf16x8(bh[qj]), Bl = as_bf16x8(bl[qj]);
+          R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, R, 0, 0, 0);
+          Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bhi[qj], Im, 0, 0, 0);
+          R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, R, 0, 0, 0);
+          Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bli[qj], Im, 0, 0, 0);
+          R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, R, 0, 0, 0);
+          Im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bhi[qj], Im, 0, 0, 0);
+        }
     }
   }
   if (!live) return;
@@ -722,13 +752,12 @@ hipError_t launch_gram_bf16x3(const Geom &g, const float2 *A, unsigned *Ahi, uns
   dim3 sgrid(g.Npad / kSplitTile, (g.K + kSplitTile - 1) / kSplitTile);
   hipLaunchKernelGGL(k_split_bf16, sgrid, dim3(256), 0, st, g.K, g.Npad, A, Ahi, Alo);
   if (blocks) {  // 2 x 2 tile blocks, one 64 x 64 tile per wave
-    const int nbB = (g.Npad / kTile + 1) / 2;
     if (t0)
-      hipExtLaunchKernelGGL(k_gram_bf16_blk, dim3(nblocks), dim3(256), 0, st, t0, t1, 0, g.K, g.Npad,
-                            nbB, static_cast<const unsigned *>(Ahi), static_cast<const unsigned *>(Alo),
+      hipExtLaunchKernelGGL(k_gram_bf16_blk<kBbRing>, dim3(nblocks), dim3(256), 0, st, t0, t1, 0, g.K, g.Npad,
+                            static_cast<const unsigned *>(Ahi), static_cast<const unsigned *>(Alo),
                             blocks, H);
     else
-      hipLaunchKernelGGL(k_gram_bf16_blk, dim3(nblocks), dim3(256), 0, st, g.K, g.Npad, nbB,
+      hipLaunchKernelGGL(k_gram_bf16_blk<kBbRing>, dim3(nblocks), dim3(256), 0, st, g.K, g.Npad,
                          static_cast<const unsigned *>(Ahi), static_cast<const unsigned *>(Alo),
                          blocks, H);
     return hipGetLastError();

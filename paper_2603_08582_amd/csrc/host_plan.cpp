@@ -270,7 +270,9 @@ Layout layout(const ofista_config *c) {
                           (c->gram_layout == OFISTA_GRAM_AUTO && L.nb >= kBfBlockMinNb);
   if (c->precision == OFISTA_PREC_SPLIT_BF16 && bf_blocked) {
     const size_t nbB = (L.nb + 1) / 2;
-    L.nbf_blocks = nbB * (nbB + 1) / 2;
+    // the launch grid: the nbB (nbB + 1) / 2 blocks padded to a multiple of
+    // 8, one run per XCD
+    L.nbf_blocks = (nbB * (nbB + 1) / 2 + 7) / 8 * 8;
     L.bf_blocks = take(L.nbf_blocks * kBytesI2);
   }
   if (c->precision == OFISTA_PREC_SPLIT_BF16) {

@@ -307,14 +307,24 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   }
   std::vector<int2> bfb;
   if (L.nbf_blocks) {
-    // 4 x 4 super-blocks, row-major over super-blocks
-    const int nbB = (nb + 1) / 2, S = 4, ns = (nbB + S - 1) / S;
-    bfb.reserve(L.nbf_blocks);
+    // 8 x 8 super-blocks, row-major over super-blocks; launch block b runs on
+    // XCD b % 8, so entry b of the table is list entry (b % 8) per + b / 8:
+    // each XCD works through a contiguous run of the list, and its ~64
+    // concurrent blocks (about one super-block) use 32 panels
+    const int nbB = (nb + 1) / 2, S = 8, ns = (nbB + S - 1) / S;
+    std::vector<int2> list;
+    list.reserve(L.nbf_blocks);
     for (int P = 0; P < ns; ++P)
       for (int Qs = P; Qs < ns; ++Qs)
         for (int IB = P * S; IB < std::min(nbB, P * S + S); ++IB)
           for (int JB = std::max(IB, Qs * S); JB < std::min(nbB, Qs * S + S); ++JB)
-            bfb.push_back(make_int2(IB, JB));
+            list.push_back(make_int2(IB, JB));
+    const size_t per = L.nbf_blocks / 8;
+    bfb.assign(L.nbf_blocks, make_int2(-1, -1));
+    for (size_t b = 0; b < L.nbf_blocks; ++b) {
+      const size_t k = (b % 8) * per + b / 8;
+      if (k < list.size()) bfb[b] = list[k];
+    }
     c->bf_blocks = reinterpret_cast<const int2 *>(base + L.bf_blocks);
   }
   if (L.gsplit > 0) {
