@@ -81,6 +81,24 @@ enum { OFISTA_PREC_FP32 = 0, OFISTA_PREC_SPLIT_BF16 = 1 };
    BLOCK = 2 x 2 tiles per workgroup (a whole tile per wave).  Must be AUTO
    with FP32 (else OFISTA_E_UNSUPPORTED). */
 enum { OFISTA_GRAM_AUTO = 0, OFISTA_GRAM_TILE = 1, OFISTA_GRAM_BLOCK = 2 };
+/* How the FISTA steps of a reconstruct call run (the same iterates bit for
+   bit either way):
+   LAUNCHES = two kernel launches per step (the pass over the H tiles, then
+     the shrink / momentum / power update);
+   RESIDENT = one cooperative launch per call (up to 64 steps; more run as
+     several launches), one workgroup per CU, the two phases of every step
+     separated by grid barriers; each workgroup keeps its share of the H
+     tiles resident (partly in LDS) across the steps.  Needs a device with
+     cooperative launch, storage GRAM and at most 5 work items (runs of two
+     tiles of a tile row) per CU (on 256 CUs: up to 70 tile rows, M <= 4480;
+     else OFISTA_E_UNSUPPORTED at create); a reconstruct that records for
+     ofista_backward uses LAUNCHES.
+     If a grid barrier times out (a launch that was not co-resident), the
+     results of that call are invalid and the next ofista_state returns
+     OFISTA_E_HIP;
+   AUTO = LAUNCHES (the faster of the two on MI355X: at M = 4096, 17.6 us
+     against 26 us per step). */
+enum { OFISTA_STEP_AUTO = 0, OFISTA_STEP_LAUNCHES = 1, OFISTA_STEP_RESIDENT = 2 };
 /* L_n rule (Section III-B asks for L >= ||sum G^H G||_2; Section III-C bounds
    its growth by ||G_n||_2^2 per pulse):
    RUNNING = rho + the sum of sigma^2 over the pulses pushed since the last
@@ -145,6 +163,7 @@ typedef struct ofista_config {
   int32_t validate_input;  /* != 0: ofista_push_pulse checks every sample of
                               d_s and returns OFISTA_E_ARG, changing nothing,
                               if one is not finite (costs a stream sync)   */
+  int32_t step_kernel;     /* OFISTA_STEP_*                                    */
 } ofista_config;
 
 typedef struct ofista_stats {
@@ -325,7 +344,9 @@ ofista_status ofista_set_lambda(struct ofista_ctx *ctx, double lambda);
    2 rows, 3 correlation (separate launch on the split-BF16 path only),
    4 scalars, 5 FISTA-step update (slot sums, shrink, momentum, power
    vector), 6 and 7 the two passes over the stored pulses of the PULSES
-   storage (G z - d, G w; then G^H of both). */
+   storage (G z - d, G w; then G^H of both), 8 the resident step kernel (one
+   launch per reconstruct call runs all its steps, tile passes and updates;
+   classes 1 and 5 then stay empty). */
 ofista_status ofista_profile(struct ofista_ctx *ctx, int32_t enable);
 ofista_status ofista_kernel_time(struct ofista_ctx *ctx, int32_t kernel,
                                  double *total_ms, int64_t *launches);

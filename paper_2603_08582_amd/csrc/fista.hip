@@ -74,9 +74,39 @@ __device__ __forceinline__ double wave_sum(double v) {
 // row; slots are read kUpdBatch at a time (index clamped in range, unused
 // values replaced by zero after the load), then the parts are summed in LDS
 // in increasing p.
-constexpr int kUpdRows = kTile / kUpdSplit;  // 32
-constexpr int kUpdParts = 256 / kUpdRows;    // 8
+constexpr int kUpdRows = kTile / kUpdSplit;  // 16
+constexpr int kUpdParts = 256 / kUpdRows;    // 16
 constexpr int kUpdBatch = 4;
+
+// The per-row arithmetic of the update (gradient step, shrink, momentum,
+// power vector and its two inner-product parts), with every fused
+// multiply-add written out so that each kernel running it rounds alike.
+struct RowUpdate {
+  float2 u, c, z, w;
+  double r, m;  // Re<w, H w> and |w'|^2 parts of this row
+};
+__device__ __forceinline__ RowUpdate row_update(float4 s, float2 z, float2 cold, float2 bi,
+                                                float2 w, float tau, float alpha, float beta,
+                                                float inv_wn) {
+  RowUpdate o;
+  const float gx = s.x - bi.x, gy = s.y - bi.y;
+  o.u = make_float2(fmaf(-tau, gx, z.x), fmaf(-tau, gy, z.y));
+  const float mag = sqrtf(fmaf(o.u.x, o.u.x, o.u.y * o.u.y));
+  float cx = 0.f, cy = 0.f;
+  if (mag > alpha) {
+    const float f = 1.f - alpha / mag;
+    cx = o.u.x * f;
+    cy = o.u.y * f;
+  }
+  o.c = make_float2(cx, cy);
+  o.z = make_float2(fmaf(beta, cx - cold.x, cx), fmaf(beta, cy - cold.y, cy));
+  o.w = make_float2(s.z * inv_wn, s.w * inv_wn);
+  o.r = fma(static_cast<double>(w.x), static_cast<double>(s.z),
+            static_cast<double>(w.y) * static_cast<double>(s.w));
+  o.m = fma(static_cast<double>(o.w.x), static_cast<double>(o.w.x),
+            static_cast<double>(o.w.y) * static_cast<double>(o.w.y));
+  return o;
+}
 
 // Slot v of target row R: the column partials j < R come first, then the run
 // starts j = R, R + chunk, ... (row partials).
@@ -150,22 +180,13 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   const float alpha = static_cast<float>(a.scal->alpha);
   double rpart = 0.0, mpart = 0.0;
   if (live) {
-    const float gx = s.x - bi.x, gy = s.y - bi.y;
-    const float ux = z.x - tau * gx, uy = z.y - tau * gy;
-    if (a.urec) a.urec[i] = make_float2(ux, uy);  // kept for the reverse pass
-    const float mag = sqrtf(ux * ux + uy * uy);
-    float cx = 0.f, cy = 0.f;
-    if (mag > alpha) {
-      const float f = 1.f - alpha / mag;
-      cx = ux * f;
-      cy = uy * f;
-    }
-    a.cn[i] = make_float2(cx, cy);
-    a.zn[i] = make_float2(cx + a.beta * (cx - cold.x), cy + a.beta * (cy - cold.y));
-    const float2 wnext = make_float2(s.z * inv_wn, s.w * inv_wn);
-    a.wn[i] = wnext;
-    rpart = static_cast<double>(w.x) * s.z + static_cast<double>(w.y) * s.w;
-    mpart = static_cast<double>(wnext.x) * wnext.x + static_cast<double>(wnext.y) * wnext.y;
+    const RowUpdate o = row_update(s, z, cold, bi, w, tau, alpha, a.beta, inv_wn);
+    if (a.urec) a.urec[i] = o.u;  // kept for the reverse pass
+    a.cn[i] = o.c;
+    a.zn[i] = o.z;
+    a.wn[i] = o.w;
+    rpart = o.r;
+    mpart = o.m;
   } else {
     a.cn[i] = make_float2(0.f, 0.f);
     a.zn[i] = make_float2(0.f, 0.f);
@@ -292,6 +313,452 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
     }
   }
   reinterpret_cast<float *>(a.Q + slot_index(J0, I, a.nb) * kTile + row0)[lane] = v[0];
+}
+
+// ---------------------------------------------------------------------------
+// Resident steps: every FISTA step of one reconstruct call in a single
+// cooperative launch of one 512-thread workgroup per CU.  A step is the same
+// two phases as the launch pair above -- the tile pass writing the slots, then
+// the update summing them -- with a grid barrier after each phase instead of a
+// kernel boundary.  Workgroup g owns work items g, g + G, g + 2G, ... (G =
+// workgroups, at most kResMaxItems items) for the whole call, in rounds of
+// two: in round r its two groups of 4 waves each take item 2r + (group).  The
+// tiles of round 0 are copied into LDS once, those of round 1 into the
+// registers of their group, and round 2 (the single-tile runs some
+// workgroups get) reads H from memory; update block 2g + (group), +2G, ...
+// follows.  The arithmetic of an item and of an update block is that of
+// k_step_tiles<2> / k_step_update<false> with the same summation orders, so
+// the iterates are bitwise those of the launch pair.  At N = 4096 on 256 CUs
+// a step measured 26 us (rounds 5.0 + 4.5 + 6.4, update 2.6, two barriers and
+// the z, w staging about 6) against 17.6 us for the launch pair, so it is an
+// option, not the default.
+//
+// Values that cross workgroups within the launch (slots, z, c, w, the power
+// parts) are written and read with agent-scope atomic stores and loads
+// (global_store / global_load with sc1): they bypass the non-coherent L1 and
+// the scalar cache, and reach the coherence point across the XCDs' L2s.  The
+// grid barrier: each workgroup waits for its own stores (the fence of
+// __syncthreads), adds 1 to the counter of its XCD group (workgroup g on
+// counter g % 8, so 32 arrivals per counter instead of 256 on one address),
+// and lanes 0..7 of the first wave poll the 8 counters until each holds its
+// workgroup count times the barrier generation.  Polls are bounded: past the
+// limit the workgroup records a fault in the scalars and stops waiting at
+// later barriers, so a launch that could not be co-resident ends instead of
+// hanging (its results are then invalid and the next state query reports the
+// fault).
+constexpr unsigned kBarSpinLimit = 1u << 20;  // polls (each ~1 us): about a second
+
+__device__ __forceinline__ float2 ld_agent2(const float2 *p) {
+  const unsigned long long v =
+      __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<float2 *>(p)),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float2, v);
+}
+__device__ __forceinline__ void st_agent2(float2 *p, float2 v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                     __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ f32x4 ld_agent4(const float4 *p) {
+  const float2 lo = ld_agent2(reinterpret_cast<const float2 *>(p));
+  const float2 hi = ld_agent2(reinterpret_cast<const float2 *>(p) + 1);
+  return f32x4{lo.x, lo.y, hi.x, hi.y};
+}
+__device__ __forceinline__ void st_agent4(float4 *p, float4 v) {
+  st_agent2(reinterpret_cast<float2 *>(p), make_float2(v.x, v.y));
+  st_agent2(reinterpret_cast<float2 *>(p) + 1, make_float2(v.z, v.w));
+}
+__device__ __forceinline__ double ld_agent_d(const double *p) {
+  const unsigned long long v =
+      __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<double *>(p)),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ void st_agent_d(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                     __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_f(float *p, float v) {
+  __hip_atomic_store(reinterpret_cast<unsigned *>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false once a wait has timed out; the caller then passes
+// broken = true to the later barriers, which no longer wait.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen, DevScalars *scal,
+                                             bool broken) {
+  __syncthreads();  // this workgroup's stores have completed
+  __shared__ unsigned timed_out;
+  if (threadIdx.x == 0) timed_out = 0;
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const unsigned nwg = gridDim.x;
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&bar[(blockIdx.x & 7) * kBarStride], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned x = threadIdx.x;
+    const unsigned target = (nwg > x ? (nwg - x + 7) / 8 : 0) * gen;
+    unsigned spins = 0;
+    while (!broken && __hip_atomic_load(&bar[x * kBarStride], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kBarSpinLimit) {
+        __hip_atomic_store(&scal->fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        timed_out = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return !broken && timed_out == 0;
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
+// not for its global stores (the fence of __syncthreads would wait for
+// those, a round trip to the coherence point per item).
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// One work item of the tile pass (tile row I, run J0..J1-1 of at most 2 tiles)
+// with its H elements from hfetch(jj, q) (row row0 + q, column lane of tile
+// J0 + jj) and z, w of row blocks I, J0, J0 + 1 from the LDS staging zs, ws
+// ([0]: block I, [1 + jj]: block J0 + jj): the multiplies, reductions and slot
+// stores of k_step_tiles<2>.
+template <typename HFetch>
+__device__ __forceinline__ void resident_item(const WorkItem it, int nb, int wave,
+                                              const float2 (*zs)[kTile],
+                                              const float2 (*ws)[kTile], float4 *Q,
+                                              float4 (*colbuf)[4][64], bool mine, HFetch hfetch) {
+  // a group without an item this round still meets the workgroup barrier
+  const int I = it.I, J0 = it.J0, J1 = it.J1;
+  const int lane = threadIdx.x & 63;
+  const int row0 = wave * kRowsPerWave;
+  const int nrun = J1 - J0;
+  float v[64];
+  if (mine) {
+    float2 zj[2], wj[2];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      zj[jj] = zs[1 + jj][lane];
+      wj[jj] = ws[1 + jj][lane];
+    }
+    float2 ryz[kRowsPerWave], ryw[kRowsPerWave];
+    float2 cz[2], cw[2];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) cz[jj] = cw[jj] = make_float2(0.f, 0.f);
+    // rows in the outer loop: each accumulator sees the same sequence of
+    // operations as in k_step_tiles (ryz[q] over jj = 0, 1; cz[jj] over q)
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      const float2 zI = zs[0][row0 + q];
+      const float2 wI = ws[0][row0 + q];
+      ryz[q] = ryw[q] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        if (jj < nrun) {
+          const float2 h = hfetch(jj, q);
+          ryz[q] = cmac(ryz[q], h, zj[jj]);
+          ryw[q] = cmac(ryw[q], h, wj[jj]);
+          cz[jj] = cmac_conj(cz[jj], h, zI);
+          cw[jj] = cmac_conj(cw[jj], h, wI);
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+      if (jj < nrun) colbuf[jj][wave][lane] = make_float4(cz[jj].x, cz[jj].y, cw[jj].x, cw[jj].y);
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      v[4 * q + 0] = ryz[q].x;
+      v[4 * q + 1] = ryz[q].y;
+      v[4 * q + 2] = ryw[q].x;
+      v[4 * q + 3] = ryw[q].y;
+    }
+#pragma unroll
+    for (int half = 32; half >= 1; half >>= 1) {
+      const bool upper = (lane & half) != 0;
+#pragma unroll
+      for (int e = 0; e < half; ++e) {
+        const float send = upper ? v[e] : v[e + half];
+        const float keep = upper ? v[e + half] : v[e];
+        v[e] = keep + __shfl_xor(send, half);
+      }
+    }
+  }
+  lds_barrier();
+  if (mine) {
+    if (wave < 2) {
+      const int jj = wave;
+      const int J = J0 + jj;
+      if (J < J1 && J != I) {
+        float4 s = colbuf[jj][0][lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+          const float4 t = colbuf[jj][w][lane];
+          s.x += t.x;
+          s.y += t.y;
+          s.z += t.z;
+          s.w += t.w;
+        }
+        st_agent4(Q + slot_index(I, J, nb) * kTile + lane, s);
+      }
+    }
+    st_agent_f(reinterpret_cast<float *>(Q + slot_index(J0, I, nb) * kTile + row0) + lane, v[0]);
+  }
+}
+
+static_assert(kChunk == 2, "resident items are runs of at most two tiles");
+
+__global__ __launch_bounds__(512) void k_steps_resident(ResidentArgs a) {
+  __shared__ float2 htile[2 * kResLdsItems][kTile * kTile];  // 128 KB
+  // the column buffers of the two item groups (tile pass) share their space
+  // with the update's reduction buffers
+  __shared__ float4 scratch_lds[2 * 2 * 4 * 64];
+  float4 (*colbuf)[2][4][64] = reinterpret_cast<float4 (*)[2][4][64]>(scratch_lds);
+  float4 (*red)[kUpdRows] = reinterpret_cast<float4 (*)[kUpdRows]>(scratch_lds);
+  static_assert(2 * kUpdParts * kUpdRows <= 2 * 2 * 4 * 64, "update buffers fit the column buffers");
+  __shared__ double wred[2][4];
+  // z and w of row blocks I, J0, J0 + 1 of every item, staged once per step
+  __shared__ float2 zst[kResMaxItems][3][kTile], wst[kResMaxItems][3][kTile];
+  __shared__ int blk[kResMaxItems][3];   // row blocks staged per item
+  __shared__ int itab[kResMaxItems][4];  // I, J0, J1, first tile index - I
+  const int G = gridDim.x, g = blockIdx.x;
+  // two groups of 4 waves; group grp works on items grp, grp + 2, grp + 4 of
+  // this workgroup, wave wig of the group on rows 16 wig ..
+  const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int grp = wave8 >> 2, wig = wave8 & 3;
+  const int lane = threadIdx.x & 63;
+  const int row0 = wig * kRowsPerWave;
+  const int nb = a.nb, nparts = a.nparts;
+  const int nmine = g < a.nitems ? min((a.nitems - g + G - 1) / G, kResMaxItems) : 0;
+  // this workgroup's items and their first tile indices, read once into
+  // LDS: a table load between the agent-scope stores of the steps would be a
+  // vector load whose wait drains those stores
+  if (threadIdx.x < kResMaxItems) {
+    const int m = threadIdx.x;
+    const WorkItem it = m < nmine ? a.items[g + m * G] : WorkItem{0, 0, 1, 0};
+    itab[m][0] = it.I;
+    itab[m][1] = it.J0;
+    itab[m][2] = it.J1;
+    itab[m][3] = a.tile_row0[it.I] - it.I;
+    blk[m][0] = it.I;
+    blk[m][1] = it.J0;
+    blk[m][2] = min(it.J0 + 1, it.J1 - 1);
+  }
+  __syncthreads();
+  auto item = [&](int m) {
+    return WorkItem{__builtin_amdgcn_readfirstlane(itab[m][0]),
+                    __builtin_amdgcn_readfirstlane(itab[m][1]),
+                    __builtin_amdgcn_readfirstlane(itab[m][2]), 0};
+  };
+  auto tile0 = [&](int m) {
+    return static_cast<size_t>(__builtin_amdgcn_readfirstlane(itab[m][3])) * (kTile * kTile);
+  };
+  // items 0, 1 (round 0) keep their tiles in LDS, items 2, 3 (round 1) in the
+  // registers of their group, item 4 (round 2) reads them from memory.  Each
+  // thread copies, and later reads back, only its own elements (rows row0..,
+  // column lane of its group's item).
+  float2 hreg[2][kRowsPerWave];
+  {
+    const int m = kResLdsItems + grp;
+    if (m < nmine) {
+      const WorkItem it = item(m);
+      const float2 *Hrow = a.H + tile0(m) + row0 * kTile + lane;
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int J = min(it.J0 + jj, it.J1 - 1);
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q)
+          hreg[jj][q] = Hrow[static_cast<size_t>(J) * kTile * kTile + q * kTile];
+      }
+    }
+  }
+  if (grp < nmine) {
+    const int m = grp;
+    const WorkItem it = item(m);
+    const float2 *Hrow = a.H + tile0(m) + row0 * kTile + lane;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int J = min(it.J0 + jj, it.J1 - 1);
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q)
+        htile[2 * m + jj][(row0 + q) * kTile + lane] =
+            Hrow[static_cast<size_t>(J) * kTile * kTile + q * kTile];
+    }
+  }
+  const float tau = static_cast<float>(a.scal->tau);
+  const float alpha = static_cast<float>(a.scal->alpha);
+  unsigned gen = a.bar_gen;
+  bool broken = false;
+  for (int k = 0; k < a.iters; ++k) {
+    const int p = (a.p0 + k) & 1;
+    const float2 *zc = (k == 0 && a.warm) ? a.cbuf[p] : a.zbuf[p];
+    const float2 *wc = a.wbuf[p], *cc = a.cbuf[p];
+    float2 *cn = a.cbuf[p ^ 1], *zn = a.zbuf[p ^ 1], *wn = a.wbuf[p ^ 1];
+    const double *slot_prev = a.slots[p];
+    double *slot_cur = a.slots[p ^ 1];
+    // stage z, w of the items' row blocks: every load issued before any is
+    // used (agent-scope loads keep their program order)
+    {
+      constexpr int kPer = (kResMaxItems * 3 * kTile + 511) / 512;
+      const int n = nmine * 3 * kTile;
+      float2 zv[kPer], wv[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 512 * u;
+        if (e < n) {
+          const int B = blk[e / (3 * kTile)][(e / kTile) % 3];
+          zv[u] = ld_agent2(zc + B * kTile + (e % kTile));
+          wv[u] = ld_agent2(wc + B * kTile + (e % kTile));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 512 * u;
+        if (e < n) {
+          (&zst[0][0][0])[e] = zv[u];
+          (&wst[0][0][0])[e] = wv[u];
+        }
+      }
+      __syncthreads();
+    }
+    // tile pass: round r, group grp takes item 2 r + grp; both groups meet
+    // at the workgroup barriers of every round (colbuf per group)
+#pragma unroll
+    for (int r = 0; r < (kResMaxItems + 1) / 2; ++r) {
+      if (2 * r >= nmine) break;
+      const int m = 2 * r + grp;
+      const bool mine = m < nmine;
+      const int mc = mine ? m : 2 * r;  // a valid index for the idle group
+      const WorkItem it = item(mc);
+      const size_t tb = tile0(mc);
+      if (r == 0) {
+        const float2 *ht = &htile[2 * grp][0];
+        resident_item(it, nb, wig, zst[mc], wst[mc], a.Q, colbuf[grp], mine,
+                      [&](int jj, int q) { return ht[jj * kTile * kTile + (row0 + q) * kTile + lane]; });
+      } else if (r == 1) {
+        resident_item(it, nb, wig, zst[mc], wst[mc], a.Q, colbuf[grp], mine,
+                      [&](int jj, int q) { return hreg[jj][q]; });
+      } else {
+        // (round 2 holds the single-tile runs of a few workgroups: H read in
+        // the multiply loop, no buffer beside the resident registers)
+        const float2 *Hrow = a.H + tb + row0 * kTile + lane;
+        resident_item(it, nb, wig, zst[mc], wst[mc], a.Q, colbuf[grp], mine, [&](int jj, int q) {
+          return Hrow[static_cast<size_t>(min(it.J0 + jj, it.J1 - 1)) * kTile * kTile + q * kTile];
+        });
+      }
+      lds_barrier();  // colbuf is reused in the next round
+    }
+    broken = !grid_barrier(a.bar, ++gen, a.scal, broken);
+    // update (k_step_update<false> per block)
+    const float beta = a.beta[k];
+    // group grp runs update block 2 g + grp (+ 2G, ...); both groups meet at
+    // the workgroup barriers
+    for (int ub0 = 2 * g; ub0 < kUpdSplit * nb; ub0 += 2 * G) {
+      const int ub = ub0 + grp;
+      const bool active = ub < kUpdSplit * nb;
+      const int ubc = active ? ub : ub0;
+      const int R = ubc / kUpdSplit, sub = ubc % kUpdSplit;
+      const int t = threadIdx.x & 255;
+      const int r = t % kUpdRows, part = t / kUpdRows;
+      const int i = R * kTile + sub * kUpdRows + r;
+      const int nvalid = R + (nb - R + kChunk - 1) / kChunk;
+      const bool live = active && t < kUpdRows && i < a.N;
+      // every load of the block is issued before any is used (agent-scope
+      // loads keep their program order): the first batch of slots, the row's
+      // vectors, the power parts
+      const float4 *q = a.Q + (i - R * kTile);
+      f32x4 x[kUpdBatch];
+#pragma unroll
+      for (int u = 0; u < kUpdBatch; ++u) {
+        const int v = part + kUpdParts * u;
+        const int vc = v < nvalid ? v : nvalid - 1;
+        x[u] = active ? ld_agent4(q + slot_index(valid_slot(vc, R, kChunk), R, nb) * kTile)
+                      : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
+      if (live) {
+        z = ld_agent2(zc + i);
+        cold = ld_agent2(cc + i);
+        bi = a.b[i];
+        w = ld_agent2(wc + i);
+      }
+      double mparts[(kResMaxParts + 255) / 256];
+#pragma unroll
+      for (int u = 0; u < (kResMaxParts + 255) / 256; ++u) {
+        const int j = t + 256 * u;
+        mparts[u] = active && j < nparts ? ld_agent_d(slot_prev + nparts + j) : 0.0;
+      }
+      double mm = 0.0;
+#pragma unroll
+      for (int u = 0; u < (kResMaxParts + 255) / 256; ++u)
+        if (t + 256 * u < nparts) mm += mparts[u];
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int v0 = part; active && v0 < nvalid; v0 += kUpdParts * kUpdBatch) {
+        if (v0 != part) {
+#pragma unroll
+          for (int u = 0; u < kUpdBatch; ++u) {
+            const int v = v0 + kUpdParts * u;
+            const int vc = v < nvalid ? v : nvalid - 1;
+            x[u] = ld_agent4(q + slot_index(valid_slot(vc, R, kChunk), R, nb) * kTile);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kUpdBatch; ++u) {
+          const bool ok = v0 + kUpdParts * u < nvalid;
+          acc.x += ok ? x[u].x : 0.f;
+          acc.y += ok ? x[u].y : 0.f;
+          acc.z += ok ? x[u].z : 0.f;
+          acc.w += ok ? x[u].w : 0.f;
+        }
+      }
+      red[grp * kUpdParts + part][r] = acc;
+      mm = wave_sum(mm);
+      if ((t & 63) == 0) wred[grp][t >> 6] = mm;
+      __syncthreads();
+      if (active && t < kUpdRows) {
+        const double wn2 = ((wred[grp][0] + wred[grp][1]) + wred[grp][2]) + wred[grp][3];
+        float4 s = red[grp * kUpdParts][t];
+#pragma unroll
+        for (int pp = 1; pp < kUpdParts; ++pp) {
+          const float4 vv = red[grp * kUpdParts + pp][t];
+          s.x += vv.x;
+          s.y += vv.y;
+          s.z += vv.z;
+          s.w += vv.w;
+        }
+        const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
+        double rpart = 0.0, mpart = 0.0;
+        if (live) {
+          const RowUpdate o = row_update(s, z, cold, bi, w, tau, alpha, beta, inv_wn);
+          st_agent2(cn + i, o.c);
+          st_agent2(zn + i, o.z);
+          st_agent2(wn + i, o.w);
+          rpart = o.r;
+          mpart = o.m;
+        } else {
+          st_agent2(cn + i, make_float2(0.f, 0.f));
+          st_agent2(zn + i, make_float2(0.f, 0.f));
+          st_agent2(wn + i, make_float2(0.f, 0.f));
+        }
+#pragma unroll
+        for (int off = kUpdRows / 2; off >= 1; off >>= 1) {
+          rpart += __shfl_xor(rpart, off);
+          mpart += __shfl_xor(mpart, off);
+        }
+        if (t == 0) {
+          st_agent_d(slot_cur + ub, rpart);
+          st_agent_d(slot_cur + nparts + ub, mpart);
+        }
+      }
+      __syncthreads();  // red / wred are reused by the next block
+    }
+    broken = !grid_barrier(a.bar, ++gen, a.scal, broken);
+  }
 }
 
 // Per-pulse scalars: lambda (first pulse), sigma^2 of position s, L_n, tau,
@@ -511,6 +978,26 @@ hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, h
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_steps_resident(const ResidentArgs &a, int nwg, hipStream_t st) {
+  if (nwg < 1 || a.iters < 1 || a.iters > kResMaxSteps) return hipErrorInvalidValue;
+  ResidentArgs args = a;
+  void *params[] = {&args};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_steps_resident), dim3(nwg),
+                                    dim3(512), params, 0, st);
+}
+
+int resident_grid(int device, int n_cu) {
+  int coop = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess ||
+      !coop)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(k_steps_resident), 512, 0) != hipSuccess ||
+      per_cu < 1)
+    return 0;
+  return n_cu;
 }
 
 hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {

@@ -183,6 +183,12 @@ ofista_status check(const ofista_config *c, std::string *why) {
     if (why) *why = "gram_layout selects among the split-BF16 Gram kernels only";
     return OFISTA_E_UNSUPPORTED;
   }
+  if (c->step_kernel < OFISTA_STEP_AUTO || c->step_kernel > OFISTA_STEP_RESIDENT)
+    return bad("unknown step_kernel");
+  if (c->step_kernel == OFISTA_STEP_RESIDENT && c->storage == OFISTA_STORE_PULSES) {
+    if (why) *why = "the resident step kernel works on the Gram storage only";
+    return OFISTA_E_UNSUPPORTED;
+  }
   if (c->precision == OFISTA_PREC_SPLIT_BF16 && c->n_freq % 32 != 0) {
     if (why) *why = "split-BF16 Gram update needs n_freq divisible by 32";
     return OFISTA_E_UNSUPPORTED;
@@ -257,6 +263,7 @@ Layout layout(const ofista_config *c) {
   L.items = take(L.nitems * sizeof(WorkItem));
   L.echo_tmp = take(L.K * kBytesD2);
   L.counter = take(sizeof(unsigned));
+  L.bar = take(8 * kBarStride * sizeof(unsigned));
   L.has_bp = c->backprojection != 0;
   if (L.has_bp) L.bp = take(static_cast<size_t>(L.npix) * kBytesC64);
   if (c->dict == OFISTA_DICT_EDGELET) {

@@ -49,7 +49,7 @@ struct DevScalars {
   double sigma2;        // ||A_s||_2^2 of the last pushed pulse
   double rho;           // Rayleigh quotient of the last FISTA step before the last push
   unsigned dbmax_bits;  // max_i |Delta b_i| of the first pulse, float bits
-  unsigned pad0;
+  unsigned fault;       // != 0: a grid barrier of the resident step kernel timed out
   double sig2_acc;      // sum of sigma^2 of the pulses pushed since that step
   double pad1;
 };
@@ -60,6 +60,7 @@ struct WorkItem {
 };
 
 constexpr size_t kAlign = 256;
+constexpr int kBarStride = 32;  // u32 between the grid-barrier counters (128 bytes)
 size_t align_up(size_t x);
 
 struct Layout {
@@ -68,6 +69,7 @@ struct Layout {
   size_t nnz = 0;  // edgelet: total pixels over all atoms
   bool has_bp = false;
   size_t bp = 0, counter = 0;
+  size_t bar = 0;  // the 8 grid-barrier counters of the resident step kernel
   // store-all comparator: capacity, stacked rows, partial rows
   bool store = false;
   int store_cap = 0, store_chunks = 0;

@@ -76,6 +76,7 @@ struct DevState {
   int *atom_ptr, *atom_pix, *pix_ptr, *pix_atom;  // edgelet tables (else NULL)
   float2 *bp;        // BP accumulator, npix (NULL when not enabled)
   unsigned *counter; // one word for ofista_count_large
+  unsigned *bar;     // 8 grid-barrier counters, kBarStride apart
   double2 *echo_tmp; // K clean-echo sums
   // split-BF16 operands of the Gram update, Npad x K words (NULL for FP32)
   unsigned *Ahi;
@@ -182,6 +183,36 @@ struct StepArgs {
   const float4 *P;
   int nchunks, Npad;
 };
+// All FISTA steps of one reconstruct call in one cooperative launch (one
+// workgroup per CU, grid barriers between the phases of a step); see
+// k_steps_resident.
+constexpr int kResMaxSteps = 64;   // steps per launch
+constexpr int kResLdsItems = 2;    // work items per workgroup whose tiles stay in LDS
+constexpr int kResRegItems = 2;    // work items per workgroup whose tiles stay in registers
+constexpr int kResMaxItems = 5;    // work items per workgroup (z, w staged in LDS per item)
+constexpr int kResMaxParts = 1024; // update parts kUpdSplit * nb (summed per thread in registers)
+struct ResidentArgs {
+  const float2 *H;
+  const WorkItem *items;
+  const int *tile_row0;
+  const float2 *b;
+  float2 *zbuf[2], *cbuf[2], *wbuf[2];
+  double *slots[2];
+  float4 *Q;
+  DevScalars *scal;
+  unsigned *bar;       // 8 arrival counters, kBarStride apart
+  unsigned bar_gen;    // barriers completed on the counters before this launch
+  int nb, N, nitems, nparts;
+  int p0;              // buffer parity of the first step
+  int iters;           // steps of this launch (<= kResMaxSteps)
+  int warm;            // != 0: the first step multiplies c (z^(1) = c_{n-1})
+  float beta[kResMaxSteps];
+};
+hipError_t launch_steps_resident(const ResidentArgs &a, int nwg, hipStream_t st);
+// Workgroups the resident step kernel needs resident at once (one per CU),
+// or 0 when the device cannot run it (no cooperative launch, or too few
+// resources per CU).
+int resident_grid(int device, int n_cu);
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,
                              hipEvent_t t1 = nullptr);
 hipError_t launch_step_update(const StepArgs &a, hipStream_t st, hipEvent_t t0 = nullptr,

@@ -22,9 +22,10 @@ PRECISION = {"fp32": 0, "split_bf16": 1}
 LIPSCHITZ = {"running": 0, "bound": 1}
 MOMENTUM = {"fista": 0, "restart": 1, "ista": 2}
 KERNEL = {"gram": 0, "step": 1, "rows": 2, "corr": 3, "scalars": 4, "update": 5,
-          "store_forward": 6, "store_adjoint": 7}
+          "store_forward": 6, "store_adjoint": 7, "resident": 8}
 STORAGE = {"gram": 0, "pulses": 1}
 GRAM_LAYOUT = {"auto": 0, "tile": 1, "block": 2}
+STEP_KERNEL = {"auto": 0, "launches": 1, "resident": 2}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_RANGE", -3: "E_STATE", -4: "E_WORKSPACE",
           -5: "E_UNSUPPORTED", -6: "E_HIP"}
@@ -54,6 +55,7 @@ class OfistaConfig(ctypes.Structure):
         ("edge_rotations_deg", ctypes.POINTER(ctypes.c_double)),
         ("backprojection", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("gram_layout", ctypes.c_int32), ("validate_input", ctypes.c_int32),
+        ("step_kernel", ctypes.c_int32),
     ]
 
 
@@ -117,7 +119,7 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
                 precision="fp32", lipschitz="running", momentum="fista",
                 record_every=0, max_pulses=0, max_iters=0, edge_lengths=(), edge_rotations=(),
                 backprojection=False, storage="gram", gram_layout="auto",
-                validate_input=False):
+                validate_input=False, step_kernel="auto"):
     """Build an OfistaConfig; returns (config, keepalive) -- keep the second
     value alive while the config is in use (it owns the host tables)."""
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
@@ -135,7 +137,8 @@ def make_config(*, n_x, n_y, x0, y0, dx, dy, positions, freq0, dfreq, n_freq,
         n_edge_rotations=rots.size,
         edge_rotations_deg=rots.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         backprojection=1 if backprojection else 0, storage=STORAGE[storage],
-        gram_layout=GRAM_LAYOUT[gram_layout], validate_input=1 if validate_input else 0)
+        gram_layout=GRAM_LAYOUT[gram_layout], validate_input=1 if validate_input else 0,
+        step_kernel=STEP_KERNEL[step_kernel])
     return cfg, (pos, lens, rots)
 
 
