@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--workload", default="haar64")
     ap.add_argument("--cpu-pulses", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-kernel", default="auto", choices=("auto", "launches", "resident"),
+                    help="how the FISTA steps run (the library's step_kernel setting)")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="BLAS threads of the oracle baseline (0: the library's default, all cores)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -171,7 +173,8 @@ def main():
     # with checkpoints plus the reverse pass for dL/dlambda and dL/dphases
     diff_mode = s.record_every > 0
     g = OnlineFista(device=dev, **(library_kwargs(wl, record_every=s.record_every, max_pulses=P,
-                                                  max_iters=m) if diff_mode else library_kwargs(wl)))
+                                                  max_iters=m) if diff_mode
+                                   else library_kwargs(wl, step_kernel=args.step_kernel)))
     stream = g.stream
 
     # a collection session (Section IV-A): Bernoulli-selected positions and an
@@ -374,6 +377,7 @@ def main():
                    "N": N, "M": M, "K": K, "pulses": pulses_per_step[0], "positions": P,
                    "inner_steps": m, "seed": s.seed,
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
+                   "step_kernel": args.step_kernel,
                    "parallelism": "single GPU"},
         "fista_iters_per_s": pulses_per_step[0] * m / (ms * 1e-3),
         "median_ms_per_step": float(np.median(step_ms_each)),

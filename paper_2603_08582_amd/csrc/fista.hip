@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   }
 }
 
-template <int CH>
+template <int CH, bool CACHED>
 __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
   __shared__ float4 colbuf[CH][4][64];
 
@@ -235,10 +235,15 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
     const int J = min(J0 + jj, J1 - 1);
 #pragma unroll
     for (int q = 0; q < kRowsPerWave; ++q) {
-      // ordinary (cached) loads: when H fits the 256 MB last-level cache it
-      // stays there from step to step (nontemporal loads measured 4% slower
-      // per pass at N = 4096)
-      h[q] = Hrow[static_cast<size_t>(J) * kTile * kTile + q * kTile];
+      // cached loads when H fits the last-level cache (it stays there from
+      // step to step), nontemporal loads when it streams from HBM
+      const float2 *ph = Hrow + static_cast<size_t>(J) * kTile * kTile + q * kTile;
+      if constexpr (CACHED) {
+        h[q] = *ph;
+      } else {
+        const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(ph));
+        h[q] = make_float2(v.x, v.y);
+      }
     }
     zz = a.zc[J * kTile + lane];
     ww = a.wc[J * kTile + lane];
@@ -964,19 +969,12 @@ hipError_t launch_scale(const float2 *x, float scale, int n, float2 *out, hipStr
 }
 
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
-  if (a.chunk == 2) {
-    if (t0)
-      hipExtLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
-    else
-      hipLaunchKernelGGL(k_step_tiles<2>, dim3(a.nitems), dim3(256), 0, st, a);
-  } else if (a.chunk == 4) {
-    if (t0)
-      hipExtLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
-    else
-      hipLaunchKernelGGL(k_step_tiles<4>, dim3(a.nitems), dim3(256), 0, st, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  if (a.chunk != 2) return hipErrorInvalidValue;
+  auto kern = a.h_cached ? k_step_tiles<2, true> : k_step_tiles<2, false>;
+  if (t0)
+    hipExtLaunchKernelGGL(kern, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
+  else
+    hipLaunchKernelGGL(kern, dim3(a.nitems), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

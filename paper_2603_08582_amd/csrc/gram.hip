@@ -708,20 +708,20 @@ constexpr bool kGramThree = true;
 
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            const GramSplit &split, hipStream_t st, hipEvent_t t0,
+                            const GramSplit &split, int kb, hipStream_t st, hipEvent_t t0,
                             hipEvent_t t1) {
-  if (g.K > kMaxFreq || ntiles_grid % 8 != 0) return hipErrorInvalidValue;
+  if (g.K > kMaxFreq || ntiles_grid % 8 != 0 || (kb != 16 && kb != 32)) return hipErrorInvalidValue;
   const bool fix = split.nsplit > 0;
-  if (fix && (split.parts < 2 || split.parts > (g.K + kGramKB - 1) / kGramKB || !split.P || !split.ij))
+  if (fix && (split.parts < 2 || split.parts > (g.K + kb - 1) / kb || !split.P || !split.ij))
     return hipErrorInvalidValue;
   // the events bracket both launches, so a timed Gram update includes the fix-up
+  auto kern = kb == 32 ? k_gram_fp32<32, kGramThree> : k_gram_fp32<16, kGramThree>;
   if (t0)
-    hipExtLaunchKernelGGL(k_gram_fp32<kGramKB, kGramThree>, dim3(ntiles_grid), dim3(256), 0, st, t0,
-                          fix ? nullptr : t1, 0, g.K, g.Npad, ntiles_grid, A, tile_ij, H, corr,
-                          split.P, split.parts);
+    hipExtLaunchKernelGGL(kern, dim3(ntiles_grid), dim3(256), 0, st, t0, fix ? nullptr : t1, 0, g.K,
+                          g.Npad, ntiles_grid, A, tile_ij, H, corr, split.P, split.parts);
   else
-    hipLaunchKernelGGL((k_gram_fp32<kGramKB, kGramThree>), dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad,
-                       ntiles_grid, A, tile_ij, H, corr, split.P, split.parts);
+    hipLaunchKernelGGL(kern, dim3(ntiles_grid), dim3(256), 0, st, g.K, g.Npad, ntiles_grid, A,
+                       tile_ij, H, corr, split.P, split.parts);
   if (fix) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -98,7 +98,7 @@ constexpr int kSplitParts = 8;
 void plan_gram_split(Layout &L) {
   L.gram_grid = L.ntiles_grid;
   const size_t q = L.ntiles / kGramCUs, rem = L.ntiles % kGramCUs;
-  const int parts = std::min((L.K + kGramKB - 1) / kGramKB, kSplitParts);
+  const int parts = std::min((L.K + L.gram_kb - 1) / L.gram_kb, kSplitParts);
   if (q < 2 || q >= kSplitMaxRounds || rem == 0 || parts < 2 || rem > L.ntiles - L.nb) return;
   L.gsplit = rem;
   L.gparts = parts;
@@ -220,6 +220,11 @@ Layout layout(const ofista_config *c) {
   L.ntiles = L.store ? 0 : static_cast<size_t>(L.nb) * (L.nb + 1) / 2;
   L.ntiles_grid = (L.ntiles + 7) / 8 * 8;
   L.gram_grid = L.ntiles_grid;
+  {
+    const size_t hbytes = L.ntiles * kTile * kTile * kBytesC64;
+    L.gram_kb = hbytes <= kLlcBytes / 2 ? kGramKBSmall : kGramKBLarge;
+    L.h_cached = hbytes <= kLlcBytes;
+  }
   if (!L.store && c->precision == OFISTA_PREC_FP32) plan_gram_split(L);
   L.chunk = pick_chunk(L.nb);
   L.nparts = kUpdSplit * L.nb;

@@ -23,8 +23,16 @@ constexpr int kChunk = 2;
 // Workgroups per tile row in the FISTA update; the power-iteration parts
 // (slots) are kept per update workgroup: nparts = kUpdSplit * nb.
 constexpr int kUpdSplit = 4;
-// Frequencies staged per LDS step of the Gram update.
-constexpr int kGramKB = 32;
+// Frequencies staged per LDS step of the FP32 Gram update, and whether the
+// FISTA tile pass reads H with cached loads, by the size of the packed H
+// against the 256 MB last-level cache.  Cached loads while H fits it (H then
+// stays there from step to step), nontemporal loads beyond: N = 4096 (68 MB)
+// 4% faster cached, M = 7808 (244 MB) 38.3 vs 43.8 us, N = 16384 (1.07 GB)
+// 189.7 us nontemporal vs 204.1 cached.  32-frequency Gram stages up to half
+// the cache, 16 beyond: N = 4096 124 vs 131 us, M = 7808 395 vs 404 us,
+// N = 16384 3.43 vs 3.61 ms.
+constexpr size_t kLlcBytes = size_t(256) << 20;
+constexpr int kGramKBSmall = 32, kGramKBLarge = 16;
 
 // Largest number of frequencies per pulse.
 constexpr int kMaxFreq = 1024;
@@ -81,6 +89,8 @@ struct Layout {
   // FP32 Gram remainder split: split tiles, pieces per tile, launch grid
   size_t gsplit = 0, gram_grid = 0, gP = 0, gsplit_ij = 0;
   int gparts = 0;
+  int gram_kb = kGramKBSmall;  // frequencies per LDS stage of the FP32 Gram update
+  bool h_cached = true;        // the tile pass reads H with cached loads
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
       sig2, gtoep, tile_ij, tile_row0, items, echo_tmp, Ahi, Alo;

@@ -151,7 +151,7 @@ struct GramSplit {
 };
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            const GramSplit &split, hipStream_t st, hipEvent_t t0 = nullptr,
+                            const GramSplit &split, int kb, hipStream_t st, hipEvent_t t0 = nullptr,
                             hipEvent_t t1 = nullptr);
 hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
                                const int *ii, const int *jj, float2 *out, hipStream_t st);
@@ -177,6 +177,7 @@ struct StepArgs {
   const int *tile_row0;
   float2 *urec;  // if set, the update stores u = z - tau (H z - b) here
   int nb, N, nitems, chunk;
+  int h_cached;  // tile pass: cached (H fits the last-level cache) or nontemporal H loads
   float beta;
   // store-all comparator: the update sums nchunks partial rows of P (stride
   // Npad) instead of the tile-pass slots

@@ -495,7 +495,7 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
     const GramSplit split{c->gP, c->gsplit_ij, static_cast<int>(L.gsplit), L.gparts};
     OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.gram_grid), corr, split,
-                              c->st, p.t0(), p.t1()));
+                              L.gram_kb, c->st, p.t0(), p.t1()));
   }
   {
     ProfScope p(c, kProfScalars);
@@ -623,6 +623,7 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.N = L.N;
     a.nitems = static_cast<int>(L.nitems);
     a.chunk = L.chunk;
+    a.h_cached = L.h_cached;
     a.beta = static_cast<float>(beta);
     if (L.store) {
       // gradient from the n stored pulses: two passes over the stacked rows
@@ -830,6 +831,7 @@ ofista_status reverse_pulse(ofista_ctx *c, int n, int j) {
     sa.N = L.N;
     sa.nitems = static_cast<int>(L.nitems);
     sa.chunk = L.chunk;
+    sa.h_cached = L.h_cached;
     OF_CK(c, launch_step_tiles(sa, c->st));
     a.ubar_cur = ubar[cur];
     a.cpart_cur = cpart[cur];
