@@ -766,47 +766,10 @@ __global__ __launch_bounds__(512) void k_steps_resident(ResidentArgs a) {
   }
 }
 
-// Per-pulse scalars: lambda (first pulse), sigma^2 of position s, L_n, tau,
-// alpha.  L_n (RUNNING) = rho + the sigma^2 of every pulse pushed since the
-// last FISTA step (Weyl: lambda_max(H + sum dH) <= lambda_max(H) + sum
-// ||dH||_2), rho the Rayleigh quotient of that step's power vector, formed
-// here from its slots when steps ran since the previous push (new_rho) and
-// kept from then on otherwise.  BOUND: L_{n-1} + sigma_n^2.  One 256-thread
-// workgroup; the slot sums use the same fixed-order tree as the step epilogue.
-__global__ __launch_bounds__(256) void k_scalars(DevScalars *scal, const double *sig2, int s,
-                                                 int first, int rel, double lam_in, int lip,
-                                                 int new_rho, const double *slot_r,
-                                                 const double *slot_m, int nparts) {
+// Per-pulse scalars as their own launch (one 256-thread workgroup).
+__global__ __launch_bounds__(256) void k_scalars(ScalarArgs a) {
   __shared__ double red[256];
-  double rho = 0.0;
-  if (new_rho) {
-    double pr = 0.0, pm = 0.0;
-    for (int j = threadIdx.x; j < nparts; j += 256) {
-      pr += slot_r[j];
-      pm += slot_m[nparts + j];
-    }
-    const double rs = block_sum256(pr, red);
-    const double ms = block_sum256(pm, red);
-    rho = rs / ms;
-  }
-  if (threadIdx.x != 0) return;
-  if (first) {
-    scal->lam = rel ? lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : lam_in;
-  }
-  const double sigma2 = sig2[s];
-  double acc = sigma2;
-  if (new_rho) {
-    scal->rho = rho;
-  } else {
-    rho = scal->rho;
-    acc += scal->sig2_acc;
-  }
-  const double L = lip == 0 ? rho + acc : scal->L + sigma2;
-  scal->sig2_acc = acc;
-  scal->sigma2 = sigma2;
-  scal->L = L;
-  scal->tau = 1.0 / L;
-  scal->alpha = scal->lam / L;
+  pulse_scalars(a, red);
 }
 
 __global__ void k_fill(unsigned *p, size_t n, unsigned value) {
@@ -1044,11 +1007,8 @@ hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, flo
   return hipGetLastError();
 }
 
-hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s, int first, int rel,
-                          double lam_in, int lip, int new_rho, const double *slot_r,
-                          const double *slot_m, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, st, scal, sig2, s, first, rel, lam_in,
-                     lip, new_rho, slot_r, slot_m, nparts);
+hipError_t launch_scalars(const ScalarArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -237,11 +237,19 @@ __global__ __launch_bounds__(256) void k_gram_fp32(int K, int Npad, int ntiles_g
 }
 
 // H(I, J) += sum over pieces p = 0..parts-1 of P[s][p], in increasing p, for
-// split tile s = blockIdx.x; 16 workgroups of 256 elements per tile.
+// split tile s = blockIdx.x; 16 workgroups of 256 elements per tile.  With
+// SCAL, workgroup (nsplit, 0) of a grid one column wider runs the pulse
+// scalars instead (they read only what earlier launches wrote).
+template <bool SCAL>
 __global__ __launch_bounds__(256) void k_gram_fixup(int nb, int parts, const int2 *__restrict__ ij,
                                                     const float2 *__restrict__ P,
-                                                    float2 *__restrict__ H) {
+                                                    float2 *__restrict__ H, ScalarArgs sc) {
   const int s = blockIdx.x;
+  if (SCAL && s == static_cast<int>(gridDim.x) - 1) {
+    __shared__ double red[256];
+    if (blockIdx.y == 0) pulse_scalars(sc, red);
+    return;
+  }
   const int e = blockIdx.y * 256 + threadIdx.x;
   const float2 *q = P + static_cast<size_t>(s) * parts * (kTile * kTile) + e;
   float2 acc = q[0];
@@ -708,8 +716,9 @@ constexpr bool kGramThree = true;
 
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            const GramSplit &split, int kb, hipStream_t st, hipEvent_t t0,
-                            hipEvent_t t1) {
+                            const GramSplit &split, int kb, const ScalarArgs *sc, bool *sc_done,
+                            hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (sc_done) *sc_done = false;
   if (g.K > kMaxFreq || ntiles_grid % 8 != 0 || (kb != 16 && kb != 32)) return hipErrorInvalidValue;
   const bool fix = split.nsplit > 0;
   if (fix && (split.parts < 2 || split.parts > (g.K + kb - 1) / kb || !split.P || !split.ij))
@@ -725,13 +734,17 @@ hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
   if (fix) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid(split.nsplit, kTile * kTile / 256);
+    const bool scal = sc != nullptr;
+    const ScalarArgs sa = scal ? *sc : ScalarArgs{};
+    const dim3 grid(split.nsplit + (scal ? 1 : 0), kTile * kTile / 256);
+    auto fk = scal ? k_gram_fixup<true> : k_gram_fixup<false>;
     if (t0)
-      hipExtLaunchKernelGGL(k_gram_fixup, grid, dim3(256), 0, st, nullptr, t1, 0, g.Npad / kTile,
-                            split.parts, split.ij, static_cast<const float2 *>(split.P), H);
+      hipExtLaunchKernelGGL(fk, grid, dim3(256), 0, st, nullptr, t1, 0, g.Npad / kTile, split.parts,
+                            split.ij, static_cast<const float2 *>(split.P), H, sa);
     else
-      hipLaunchKernelGGL(k_gram_fixup, grid, dim3(256), 0, st, g.Npad / kTile, split.parts,
-                         split.ij, static_cast<const float2 *>(split.P), H);
+      hipLaunchKernelGGL(fk, grid, dim3(256), 0, st, g.Npad / kTile, split.parts, split.ij,
+                         static_cast<const float2 *>(split.P), H, sa);
+    if (scal && sc_done) *sc_done = true;
   }
   return hipGetLastError();
 }

@@ -149,10 +149,14 @@ struct GramSplit {
   const int2 *ij;   // (I, J) of each split tile
   int nsplit, parts;
 };
+struct ScalarArgs;
+// With sc given and the split on, the fix-up launch also runs the pulse
+// scalars (one more workgroup) and *sc_done is set; otherwise *sc_done is
+// cleared and the caller launches them.
 hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
                             const int2 *tile_ij, int ntiles_grid, const CorrArgs &corr,
-                            const GramSplit &split, int kb, hipStream_t st, hipEvent_t t0 = nullptr,
-                            hipEvent_t t1 = nullptr);
+                            const GramSplit &split, int kb, const ScalarArgs *sc, bool *sc_done,
+                            hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_gram_entries(const Geom &g, const float2 *H, const int *tile_row0, int n,
                                const int *ii, const int *jj, float2 *out, hipStream_t st);
 hipError_t launch_gram_dense(const Geom &g, const float2 *H,
@@ -230,10 +234,67 @@ hipError_t launch_store_adjoint(const float2 *G, int rows, int Npad, const float
 // out[k] = d[k] e^{-i phi}, k < K.
 hipError_t launch_rotate(const float2 *d, int K, double cos_c, double sin_c, float2 *out,
                          hipStream_t st);
-hipError_t launch_scalars(DevScalars *scal, const double *sig2, int s,
-                          int first, int rel, double lam_in, int lip,
-                          int new_rho, const double *slot_r,
-                          const double *slot_m, int nparts, hipStream_t st);
+// Per-pulse scalars: lambda (first pulse), sigma^2 of position s, L_n, tau,
+// alpha.  L_n (RUNNING) = rho + the sigma^2 of every pulse pushed since the
+// last FISTA step (Weyl: lambda_max(H + sum dH) <= lambda_max(H) + sum
+// ||dH||_2), rho the Rayleigh quotient of that step's power vector, formed
+// from its slots when steps ran since the previous push (new_rho) and kept
+// from then on otherwise.  BOUND: L_{n-1} + sigma_n^2.
+struct ScalarArgs {
+  DevScalars *scal;
+  const double *sig2;
+  const double *slot_r, *slot_m;  // Re<w, Hw> and |w|^2 parts of the last step
+  double lam_in;
+  int s, first, rel, lip, new_rho, nparts;
+};
+
+// The scalars as one 256-thread workgroup (its own launch, or an extra
+// workgroup of the Gram fix-up launch); the slot sums use a fixed-order tree,
+// so both places give the same bits.
+__device__ inline double scalars_tree_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline void pulse_scalars(const ScalarArgs &a, double *red) {
+  DevScalars *scal = a.scal;
+  double rho = 0.0;
+  if (a.new_rho) {
+    double pr = 0.0, pm = 0.0;
+    for (int j = threadIdx.x; j < a.nparts; j += 256) {
+      pr += a.slot_r[j];
+      pm += a.slot_m[a.nparts + j];
+    }
+    const double rs = scalars_tree_sum(pr, red);
+    const double ms = scalars_tree_sum(pm, red);
+    rho = rs / ms;
+  }
+  if (threadIdx.x != 0) return;
+  if (a.first)
+    scal->lam = a.rel ? a.lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : a.lam_in;
+  const double sigma2 = a.sig2[a.s];
+  double acc = sigma2;
+  if (a.new_rho) {
+    scal->rho = rho;
+  } else {
+    rho = scal->rho;
+    acc += scal->sig2_acc;
+  }
+  const double L = a.lip == 0 ? rho + acc : scal->L + sigma2;
+  scal->sig2_acc = acc;
+  scal->sigma2 = sigma2;
+  scal->L = L;
+  scal->tau = 1.0 / L;
+  scal->alpha = scal->lam / L;
+}
+
+hipError_t launch_scalars(const ScalarArgs &a, hipStream_t st);
 hipError_t launch_fill(void *p, size_t n_u32, unsigned value, hipStream_t st);
 // *count (zeroed by the caller) += #{m < M : |c_m| > thr} (FP32 magnitude).
 hipError_t launch_count_large(const float2 *c, int M, float thr, unsigned *count, hipStream_t st);

@@ -467,6 +467,11 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
   const DevState &d = c->d;
   const Layout &L = c->L;
   const int first = c->n == 0 ? 1 : 0;
+  const int par = static_cast<int>(c->G & 1);
+  const ScalarArgs sca{d.scal, d.sig2, d.slots[par], d.slots[par ^ 1], c->cfg.lambda, s, first,
+                       c->cfg.lambda_relative, c->cfg.lipschitz, c->step_since_push ? 1 : 0,
+                       L.nparts};
+  bool scal_done = false;
   {
     ProfScope p(c, kProfRows);
     OF_CK(c, launch_rows(c->g, d.pos, s, d.A, c->dt, c->st));
@@ -495,16 +500,13 @@ ofista_status push_impl(ofista_ctx *c, const void *d_pulse, int32_t s, double ph
                   static_cast<float>(std::sin(phase_corr)), d.b, d.scal, first};
     const GramSplit split{c->gP, c->gsplit_ij, static_cast<int>(L.gsplit), L.gparts};
     OF_CK(c, launch_gram_fp32(c->g, d.A, d.H, d.tile_ij, static_cast<int>(L.gram_grid), corr, split,
-                              L.gram_kb, c->st, p.t0(), p.t1()));
+                              L.gram_kb, &sca, &scal_done, c->st, p.t0(), p.t1()));
   }
-  {
+  if (!scal_done) {  // else the Gram fix-up launch ran them
     ProfScope p(c, kProfScalars);
-    const int par = static_cast<int>(c->G & 1);
-    OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
-                            c->cfg.lipschitz, c->step_since_push ? 1 : 0, d.slots[par],
-                            d.slots[par ^ 1], L.nparts, c->st));
-    c->step_since_push = false;
+    OF_CK(c, launch_scalars(sca, c->st));
   }
+  c->step_since_push = false;
   if (seg_j >= 0) {
     const size_t hbytes = L.ntiles * kTile * kTile * sizeof(float2);
     OF_CK(c, hipMemcpyAsync(c->base + L.seg_H + seg_j * hbytes, d.H, hbytes, hipMemcpyDeviceToDevice,
@@ -541,9 +543,10 @@ ofista_status push_store(ofista_ctx *c, const void *d_pulse, int32_t s, double p
   {
     ProfScope p(c, kProfScalars);
     const int par = static_cast<int>(c->G & 1);
-    OF_CK(c, launch_scalars(d.scal, d.sig2, s, first, c->cfg.lambda_relative, c->cfg.lambda,
-                            c->cfg.lipschitz, c->step_since_push ? 1 : 0, d.slots[par],
-                            d.slots[par ^ 1], L.nparts, c->st));
+    const ScalarArgs sca{d.scal, d.sig2, d.slots[par], d.slots[par ^ 1], c->cfg.lambda, s, first,
+                         c->cfg.lambda_relative, c->cfg.lipschitz, c->step_since_push ? 1 : 0,
+                         L.nparts};
+    OF_CK(c, launch_scalars(sca, c->st));
     c->step_since_push = false;
   }
   c->n += 1;
