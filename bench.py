@@ -3,7 +3,9 @@
 One step = one whole image: reset of the online state, then for each of the
 P = 128 pulses push_pulse (rows, Haar fold, b and Gram update, L_n) and
 reconstruct(20) (20 fused matvec/shrink/momentum steps).  Echoes are
-synthesised on the device before timing (inputs resident in HBM).
+synthesised on the device before timing (inputs resident in HBM).  The
+timed steps replay one HIP graph captured from the library's stream (the
+same kernels in the same order; --launch stream launches them one by one).
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (per-launch durations from HIP events on the library's stream) and
@@ -147,6 +149,11 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--launch", default="graph", choices=("graph", "stream"),
+                    help="graph: capture one step (reset + all pulses) from the library's "
+                         "stream into a HIP graph once and time its replays (plain Gram "
+                         "workloads; sessions and the differentiation form always launch); "
+                         "stream: launch every kernel of every step")
     ap.add_argument("--table1", action="store_true",
                     help="instead of the metric: time one pulse (push + m steps) at growing n "
                          "for the Gram (Online FISTA) and the stored-pulse comparator, with "
@@ -172,6 +179,15 @@ def main():
     # the differentiation form (record_every > 0): one step is the forward run
     # with checkpoints plus the reverse pass for dL/dlambda and dL/dphases
     diff_mode = s.record_every > 0
+    session_mode = s.bernoulli_p < 1.0 or s.ideal_count > 0
+    # sessions take host decisions between pulses and the differentiation form
+    # synchronises inside its step: those launch from the stream
+    graph_mode = (args.launch == "graph" and not diff_mode and not session_mode
+                  and args.step_kernel != "resident")
+    if graph_mode:
+        # capture needs a stream other than the null stream; everything of
+        # this run goes to it, so no cross-stream ordering is involved
+        torch.cuda.set_stream(torch.cuda.Stream(dev))
     g = OnlineFista(device=dev, **(library_kwargs(wl, record_every=s.record_every, max_pulses=P,
                                                   max_iters=m) if diff_mode
                                    else library_kwargs(wl, step_kernel=args.step_kernel)))
@@ -179,7 +195,6 @@ def main():
 
     # a collection session (Section IV-A): Bernoulli-selected positions and an
     # early stop at the ideal large-coefficient count; otherwise every position
-    session_mode = s.bernoulli_p < 1.0 or s.ideal_count > 0
     if session_mode:
         from paper_2603_08582_amd import session as sess
         sched = sess.bernoulli_schedule(wl.select_u, s.bernoulli_p)
@@ -253,10 +268,18 @@ def main():
     torch.cuda.synchronize()
     if diff_mode:  # the split covers the timed steps only (the first run loads code)
         diff_split.update(forward_ms=0.0, loss_ms=0.0, backward_ms=0.0, n=0)
+    timed = step
+    if graph_mode:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            step()
+        graph.replay()  # first replay uploads the graph: untimed
+        torch.cuda.synchronize()
+        timed = graph.replay
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev[0].record(stream)
     for k in range(args.steps):
-        step()
+        timed()
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[-1]) / args.steps
@@ -378,6 +401,8 @@ def main():
                    "inner_steps": m, "seed": s.seed,
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
                    "step_kernel": args.step_kernel,
+                   "launch": "HIP graph replay of the captured step" if graph_mode
+                             else "stream launches",
                    "parallelism": "single GPU"},
         "fista_iters_per_s": pulses_per_step[0] * m / (ms * 1e-3),
         "median_ms_per_step": float(np.median(step_ms_each)),

@@ -28,6 +28,14 @@
  * - Every call that takes a ctx enqueues its device work on the stream given
  *   to ofista_create and returns without waiting, unless stated otherwise.
  * - A ctx is single-threaded: calls on one ctx must not overlap.
+ * - ofista_reset, ofista_push_pulse (without validate_input),
+ *   ofista_reconstruct and ofista_reconstruct_static (launch-pair step kernel)
+ *   enqueue kernels and device-to-device copies only: no host
+ *   synchronisation and no memset, so a sequence of them can be captured from
+ *   the ctx's stream into a HIP graph and replayed.  The host side of the ctx
+ *   (pulse count, step parity, momentum t) advances when the calls are made,
+ *   not when the graph replays: begin a captured sequence with ofista_reset,
+ *   and make no other state-changing call on the ctx between replays.
  * - Errors are returned as ofista_status; nothing throws or aborts across the
  *   ABI.  After OFISTA_E_HIP the ctx is poisoned and every later call on it
  *   returns OFISTA_E_STATE (ofista_destroy still works).
@@ -342,7 +350,9 @@ ofista_status ofista_set_lambda(struct ofista_ctx *ctx, double lambda);
    frequency pieces, the pair of events spans the Gram launch and the launch
    that adds the pieces to H), 1 FISTA-step tile pass (the H z / H w streaming),
    2 rows, 3 correlation (separate launch on the split-BF16 path only),
-   4 scalars, 5 FISTA-step update (slot sums, shrink, momentum, power
+   4 scalars (their own launch only where the FP32 Gram update has no
+   fix-up launch; otherwise they run as one more workgroup of it and are
+   timed with class 0), 5 FISTA-step update (slot sums, shrink, momentum, power
    vector), 6 and 7 the two passes over the stored pulses of the PULSES
    storage (G z - d, G w; then G^H of both), 8 the resident step kernel (one
    launch per reconstruct call runs all its steps, tile passes and updates;
