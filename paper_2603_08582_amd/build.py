@@ -5,7 +5,8 @@
 Every HIP source is compiled with packed-FP32 instructions disabled
 (-target-feature -packed-fp32-ops) and linked into one shared library next
 to this file.  The test suite's plain-C driver of the ABI (tests/c) is built
-against it with the host C compiler.  The oracle's C parts (if any) are built
+against it with the host C compiler, and the plain streaming-read reference
+(tests/c/read_ceiling.hip) with hipcc.  The oracle's C parts (if any) are built
 by __graft_entry__.
 """
 
@@ -80,6 +81,22 @@ def build_c_driver(lib: Path = LIB) -> Path:
     return exe
 
 
+READ_CEILING = HERE.parent / "tests" / "c" / "read_ceiling.hip"
+
+
+def build_read_ceiling() -> Path:
+    """Compile tests/c/read_ceiling.hip (the plain streaming-read reference
+    the tile pass is compared with; no library code)."""
+    exe = READ_CEILING.with_suffix("")
+    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           str(READ_CEILING), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"read_ceiling build failed:\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 def build(verbose: bool = False) -> Path:
     with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -91,9 +108,11 @@ def build(verbose: bool = False) -> Path:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     exe = build_c_driver(LIB)
+    rc_exe = build_read_ceiling()
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
         print(f"built {exe}", file=sys.stderr)
+        print(f"built {rc_exe}", file=sys.stderr)
     return LIB
 
 

@@ -1,0 +1,131 @@
+// Read ceiling: what a plain streaming read of B bytes attains on this GPU,
+// for comparison with the FISTA tile pass, which reads the packed upper
+// triangle of H (4M(M+1) bytes) once per step.
+//
+//     read_ceiling [MBYTES ...]
+//
+// With no arguments the sizes are those of H at M = 4096, 7808 and 16384
+// coefficients (67.1, 243.9 and 1073.8 MB).  For each size and launch shape
+// (workgroups x threads, cached or nontemporal loads) the kernel sums the
+// buffer as 16-byte vectors, grid-stride with four loads in flight per
+// thread, and writes one partial per workgroup; launches run back to back on
+// one stream, each bracketed by events, and the median and mean per launch
+// are printed with the byte rate.  The buffer is zero-filled first and the
+// first launches are untimed, so a buffer that fits the last-level cache is
+// served from there, as H is between FISTA steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int T, bool NT>
+__global__ __launch_bounds__(T) void k_read(const f32x4 *__restrict__ p, size_t n16,
+                                            float *__restrict__ out) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const size_t stride = static_cast<size_t>(gridDim.x) * T;
+  size_t i = static_cast<size_t>(blockIdx.x) * T + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    f32x4 a, b, c, d;
+    if constexpr (NT) {
+      a = __builtin_nontemporal_load(p + i);
+      b = __builtin_nontemporal_load(p + i + stride);
+      c = __builtin_nontemporal_load(p + i + 2 * stride);
+      d = __builtin_nontemporal_load(p + i + 3 * stride);
+    } else {
+      a = p[i];
+      b = p[i + stride];
+      c = p[i + 2 * stride];
+      d = p[i + 3 * stride];
+    }
+    acc += (a + b) + (c + d);
+  }
+  for (; i < n16; i += stride) acc += p[i];
+  __shared__ float red[T];
+  red[threadIdx.x] = (acc.x + acc.y) + (acc.z + acc.w);
+  __syncthreads();
+  for (int o = T / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+#define CHECK(x)                                                                 \
+  do {                                                                           \
+    const hipError_t err_ = (x);                                                 \
+    if (err_ != hipSuccess) {                                                    \
+      std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(err_), \
+                   __LINE__);                                                    \
+      std::exit(1);                                                              \
+    }                                                                            \
+  } while (0)
+
+constexpr int kMaxGrid = 8192;
+
+template <int T, bool NT>
+void time_read(const f32x4 *p, size_t bytes, int grid, float *out, int reps) {
+  const size_t n16 = bytes / 16;
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto &e : ev) CHECK(hipEventCreate(&e));
+  for (int w = 0; w < 5; ++w) hipLaunchKernelGGL((k_read<T, NT>), dim3(grid), dim3(T), 0, 0, p, n16, out);
+  CHECK(hipGetLastError());
+  CHECK(hipDeviceSynchronize());
+  for (int r = 0; r < reps; ++r) {
+    CHECK(hipEventRecord(ev[2 * r], 0));
+    hipLaunchKernelGGL((k_read<T, NT>), dim3(grid), dim3(T), 0, 0, p, n16, out);
+    CHECK(hipEventRecord(ev[2 * r + 1], 0));
+  }
+  CHECK(hipGetLastError());
+  CHECK(hipDeviceSynchronize());
+  std::vector<float> ms(reps);
+  double total = 0.0;
+  for (int r = 0; r < reps; ++r) {
+    CHECK(hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1]));
+    total += ms[r];
+  }
+  std::sort(ms.begin(), ms.end());
+  const double med_us = ms[reps / 2] * 1e3, mean_us = total / reps * 1e3;
+  std::printf("%10.1f MB  %4d threads  %s  %5d workgroups : median %9.2f us (%5.0f GB/s), "
+              "mean %9.2f us (%5.0f GB/s)\n",
+              bytes / 1e6, T, NT ? "nontemporal" : "cached     ", grid, med_us,
+              bytes / med_us / 1e3, mean_us, bytes / mean_us / 1e3);
+  for (auto &e : ev) CHECK(hipEventDestroy(e));
+}
+
+int main(int argc, char **argv) {
+  std::vector<size_t> sizes;
+  for (int a = 1; a < argc; ++a) {
+    const double mb = std::atof(argv[a]);
+    if (!(mb > 0.0) || mb > 65536.0) {
+      std::fprintf(stderr, "usage: read_ceiling [MBYTES ...] (each in (0, 65536])\n");
+      return 2;
+    }
+    sizes.push_back(static_cast<size_t>(mb * 1e6) / 16 * 16);
+  }
+  if (sizes.empty()) {
+    for (const size_t m : {size_t{4096}, size_t{7808}, size_t{16384}}) sizes.push_back(4 * m * (m + 1));
+  }
+  const size_t maxb = *std::max_element(sizes.begin(), sizes.end());
+  f32x4 *p = nullptr;
+  float *out = nullptr;
+  CHECK(hipMalloc(&p, maxb));
+  CHECK(hipMalloc(&out, kMaxGrid * sizeof(float)));
+  CHECK(hipMemset(p, 0, maxb));
+  CHECK(hipDeviceSynchronize());
+  for (const size_t b : sizes) {
+    const int reps = b > (size_t{512} << 20) ? 40 : 200;
+    for (const int g : {1024, 2048, 4096, kMaxGrid}) {
+      time_read<256, false>(p, b, g, out, reps);
+      time_read<256, true>(p, b, g, out, reps);
+    }
+    for (const int g : {1024, 2048}) time_read<512, false>(p, b, g, out, reps);
+  }
+  CHECK(hipFree(p));
+  CHECK(hipFree(out));
+  std::printf("done\n");
+  return 0;
+}

@@ -72,6 +72,30 @@ def test_driver_compiles_as_c_and_rejects_bad_input(tmp_path):
     assert r.returncode == 2 and "invalid configuration" in r.stderr
 
 
+def test_read_ceiling_builds_and_rejects_bad_sizes():
+    """The plain streaming-read reference (tests/c/read_ceiling.hip) is built by
+    the package build and checks its arguments before any GPU call."""
+    exe = ROOT / "tests" / "c" / "read_ceiling"
+    if not exe.exists():
+        pytest.skip("read_ceiling not built")
+    for bad in ("-5", "0", "x", "70000"):
+        r = subprocess.run([str(exe), bad], capture_output=True, text=True)
+        assert r.returncode == 2 and "usage" in r.stderr, bad
+
+
+@pytest.mark.gpu
+def test_read_ceiling_runs():
+    """One small size through every launch shape (a smoke run of the timing
+    program that profiles/read-ceiling.md comes from)."""
+    exe = ROOT / "tests" / "c" / "read_ceiling"
+    if not exe.exists():
+        pytest.skip("read_ceiling not built")
+    r = subprocess.run([str(exe), "8"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stdout.splitlines() if "GB/s" in ln]
+    assert len(lines) == 10 and r.stdout.strip().endswith("done")
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("dictionary", ["identity", "haar"])
 def test_driver_matches_binding_and_oracle(tmp_path, dictionary):
