@@ -78,8 +78,9 @@ def test_read_ceiling_builds_and_rejects_bad_sizes():
     exe = ROOT / "tests" / "c" / "read_ceiling"
     if not exe.exists():
         pytest.skip("read_ceiling not built")
-    for bad in ("-5", "0", "x", "70000"):
-        r = subprocess.run([str(exe), bad], capture_output=True, text=True)
+    for bad in (["-5"], ["0"], ["x"], ["70000"], ["--tiles"], ["--tiles", "10"],
+                ["--tiles", "40000"]):
+        r = subprocess.run([str(exe), *bad], capture_output=True, text=True)
         assert r.returncode == 2 and "usage" in r.stderr, bad
 
 
@@ -94,6 +95,11 @@ def test_read_ceiling_runs():
     assert r.returncode == 0, r.stderr
     lines = [ln for ln in r.stdout.splitlines() if "GB/s" in ln]
     assert len(lines) == 10 and r.stdout.strip().endswith("done")
+    # the tile-pattern read on a ragged tile count (M = 200: 4 tile rows, 10 tiles)
+    r = subprocess.run([str(exe), "--tiles", "200"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stdout.splitlines() if "GB/s" in ln]
+    assert len(lines) == 2 and all("6 work items" in ln for ln in lines), r.stdout
 
 
 @pytest.mark.gpu
