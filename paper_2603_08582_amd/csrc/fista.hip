@@ -122,34 +122,44 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   const int nb = a.nb, chunk = a.chunk, nparts = kUpdSplit * nb;
   const int t = threadIdx.x;
   const int r = t % kUpdRows, part = t / kUpdRows;
+  // step and threshold read first: a load after the barrier below would be
+  // a round trip of its own at the end of the kernel
+  const float tau = static_cast<float>(a.scal->tau);
+  const float alpha = static_cast<float>(a.scal->alpha);
   const int i = R * kTile + sub * kUpdRows + r;
   // tile-pass slots: column partials j < R, then the run starts; store-all:
   // the nchunks partial rows of P
   const int nvalid = PARTIALS ? a.nchunks : R + (nb - R + chunk - 1) / chunk;
-  // this row's inputs, loaded before the slots so both arrive together
   const bool live = t < kUpdRows && i < a.N;
-  float2 z = make_float2(0.f, 0.f), cold = z, bi = z, w = z;
-  if (live) {
-    z = a.zc[i];
-    cold = a.cc[i];
-    bi = a.b[i];
-    w = a.wc[i];
-  }
-  // |w|^2 parts of the vector this step multiplied
-  double m = 0.0;
-  for (int j = t; j < nparts; j += 256) m += a.slot_prev[nparts + j];
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const f32x4 *q = PARTIALS ? reinterpret_cast<const f32x4 *>(a.P + i)
                             : reinterpret_cast<const f32x4 *>(a.Q + (i - R * kTile));
-  for (int v0 = part; v0 < nvalid; v0 += kUpdParts * kUpdBatch) {
-    f32x4 x[kUpdBatch];
+  auto slot_off = [&](int v) {
+    const int vc = v < nvalid ? v : nvalid - 1;
+    return PARTIALS ? static_cast<size_t>(vc) * a.Npad
+                    : slot_index(valid_slot(vc, R, chunk), R, nb) * kTile;
+  };
+  // Every load of the first round is issued before any value is used (the
+  // first batch of slots, the row's vectors, the first |w|^2 part of the
+  // vector this step multiplied): one round trip instead of three.  Indices
+  // are clamped in range and unused values dropped afterwards (i < Npad for
+  // every thread; threads past nvalid or nparts add zeros, as the loops below
+  // would have added nothing).
+  f32x4 x[kUpdBatch];
 #pragma unroll
-    for (int u = 0; u < kUpdBatch; ++u) {
-      const int v = v0 + kUpdParts * u;
-      const int vc = v < nvalid ? v : nvalid - 1;
-      const size_t off = PARTIALS ? static_cast<size_t>(vc) * a.Npad
-                                  : slot_index(valid_slot(vc, R, chunk), R, nb) * kTile;
-      x[u] = __builtin_nontemporal_load(q + off);
+  for (int u = 0; u < kUpdBatch; ++u) x[u] = __builtin_nontemporal_load(q + slot_off(part + kUpdParts * u));
+  const float2 zl = a.zc[i], coldl = a.cc[i], bil = a.b[i], wl = a.wc[i];
+  const double m0 = a.slot_prev[nparts + (t < nparts ? t : 0)];
+  const float2 zero2 = make_float2(0.f, 0.f);
+  const float2 z = live ? zl : zero2, cold = live ? coldl : zero2, bi = live ? bil : zero2,
+               w = live ? wl : zero2;
+  double m = 0.0;
+  if (t < nparts) m += m0;
+  for (int j = t + 256; j < nparts; j += 256) m += a.slot_prev[nparts + j];
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int v0 = part;; v0 += kUpdParts * kUpdBatch) {
+    if (v0 != part) {
+#pragma unroll
+      for (int u = 0; u < kUpdBatch; ++u) x[u] = __builtin_nontemporal_load(q + slot_off(v0 + kUpdParts * u));
     }
 #pragma unroll
     for (int u = 0; u < kUpdBatch; ++u) {
@@ -159,6 +169,7 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
       acc.z += ok ? x[u].z : 0.f;
       acc.w += ok ? x[u].w : 0.f;
     }
+    if (v0 + kUpdParts * kUpdBatch >= nvalid) break;
   }
   red[part][r] = acc;
   m = wave_sum(m);
@@ -176,8 +187,6 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
     s.w += v.w;
   }
   const float inv_wn = static_cast<float>(1.0 / sqrt(wn2));
-  const float tau = static_cast<float>(a.scal->tau);
-  const float alpha = static_cast<float>(a.scal->alpha);
   double rpart = 0.0, mpart = 0.0;
   if (live) {
     const RowUpdate o = row_update(s, z, cold, bi, w, tau, alpha, a.beta, inv_wn);
@@ -228,8 +237,7 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
     ryw[q] = make_float2(0.f, 0.f);
   }
 
-  const int trow = a.tile_row0[I];
-  const float2 *Hrow = a.H + static_cast<size_t>(trow - I) * (kTile * kTile) + row0 * kTile + lane;
+  const float2 *Hrow = a.H + static_cast<size_t>(it.toff) * (kTile * kTile) + row0 * kTile + lane;
   float2 hA[kRowsPerWave], hB[kRowsPerWave], zA, wA, zB, wB;
   auto issue = [&](float2 (&h)[kRowsPerWave], float2 &zz, float2 &ww, int jj) {
     const int J = min(J0 + jj, J1 - 1);
@@ -549,7 +557,7 @@ __global__ __launch_bounds__(512) void k_steps_resident(ResidentArgs a) {
     itab[m][0] = it.I;
     itab[m][1] = it.J0;
     itab[m][2] = it.J1;
-    itab[m][3] = a.tile_row0[it.I] - it.I;
+    itab[m][3] = it.toff;
     blk[m][0] = it.I;
     blk[m][1] = it.J0;
     blk[m][2] = min(it.J0 + 1, it.J1 - 1);

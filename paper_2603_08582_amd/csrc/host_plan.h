@@ -62,9 +62,11 @@ struct DevScalars {
   double pad1;
 };
 
-// One FISTA work item: tile row I, tiles J0 .. J1-1 (J0 >= I).
+// One FISTA work item: tile row I, tiles J0 .. J1-1 (J0 >= I).  Tile (I, J)
+// sits at packed index toff + J (toff = index of (I, I) minus I), carried in
+// the item so the kernels need no second table lookup before loading H.
 struct WorkItem {
-  int I, J0, J1, pad;
+  int I, J0, J1, toff;
 };
 
 constexpr size_t kAlign = 256;

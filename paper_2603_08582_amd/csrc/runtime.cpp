@@ -345,7 +345,7 @@ ofista_status ofista_create(const ofista_config *cfg, void *d_workspace, size_t 
   items.reserve(L.nitems);
   for (int I = 0; I < nb; ++I)
     for (int J0 = I; J0 < nb; J0 += L.chunk)
-      items.push_back(WorkItem{I, J0, J0 + L.chunk < nb ? J0 + L.chunk : nb, 0});
+      items.push_back(WorkItem{I, J0, J0 + L.chunk < nb ? J0 + L.chunk : nb, row0[I] - I});
   std::stable_partition(items.begin(), items.end(),
                         [&](const WorkItem &w) { return w.J1 - w.J0 == L.chunk; });
 
