@@ -251,20 +251,29 @@ __global__ __launch_bounds__(256) void k_gram_fixup(int nb, int parts, const int
     return;
   }
   const int e = blockIdx.y * 256 + threadIdx.x;
+  // all pieces are loaded at once (indices clamped to the last piece), and H
+  // as soon as the tile's position is known; summed in increasing p
+  const int2 tij = ij[s];
   const float2 *q = P + static_cast<size_t>(s) * parts * (kTile * kTile) + e;
-  float2 acc = q[0];
-  for (int p = 1; p < parts; ++p) {
-    const float2 v = q[static_cast<size_t>(p) * (kTile * kTile)];
-    acc.x += v.x;
-    acc.y += v.y;
-  }
-  const int I = ij[s].x, J = ij[s].y;
+  float2 v[kGramSplitMaxParts];
+#pragma unroll
+  for (int p = 0; p < kGramSplitMaxParts; ++p)
+    v[p] = q[static_cast<size_t>(p < parts ? p : parts - 1) * (kTile * kTile)];
+  const int I = tij.x, J = tij.y;
   const size_t tile_index = static_cast<size_t>(I) * nb - static_cast<size_t>(I) * (I - 1) / 2 + (J - I);
   float2 *h = H + tile_index * (kTile * kTile) + e;
-  float2 v = *h;
-  v.x += acc.x;
-  v.y += acc.y;
-  *h = v;
+  float2 hv = *h;
+  float2 acc = v[0];
+#pragma unroll
+  for (int p = 1; p < kGramSplitMaxParts; ++p) {
+    if (p < parts) {
+      acc.x += v[p].x;
+      acc.y += v[p].y;
+    }
+  }
+  hv.x += acc.x;
+  hv.y += acc.y;
+  *h = hv;
 }
 
 constexpr int kCorrPix = 32;    // pixels per workgroup
@@ -721,7 +730,8 @@ hipError_t launch_gram_fp32(const Geom &g, const float2 *A, float2 *H,
   if (sc_done) *sc_done = false;
   if (g.K > kMaxFreq || ntiles_grid % 8 != 0 || (kb != 16 && kb != 32)) return hipErrorInvalidValue;
   const bool fix = split.nsplit > 0;
-  if (fix && (split.parts < 2 || split.parts > (g.K + kb - 1) / kb || !split.P || !split.ij))
+  if (fix && (split.parts < 2 || split.parts > (g.K + kb - 1) / kb ||
+              split.parts > kGramSplitMaxParts || !split.P || !split.ij))
     return hipErrorInvalidValue;
   // the events bracket both launches, so a timed Gram update includes the fix-up
   auto kern = kb == 32 ? k_gram_fp32<32, kGramThree> : k_gram_fp32<16, kGramThree>;

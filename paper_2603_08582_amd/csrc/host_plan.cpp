@@ -93,7 +93,7 @@ constexpr int kBfBlockMinNb = 256;
 // resident from the start and there is no tail of lone tiles.
 constexpr size_t kGramCUs = 256;  // compute units of the MI355X
 constexpr size_t kSplitMaxRounds = 64;
-constexpr int kSplitParts = 8;
+constexpr int kSplitParts = kGramSplitMaxParts;
 
 void plan_gram_split(Layout &L) {
   L.gram_grid = L.ntiles_grid;

@@ -69,6 +69,10 @@ struct WorkItem {
   int I, J0, J1, toff;
 };
 
+// Most frequency pieces one split remainder tile of the FP32 Gram update is
+// cut into (the fix-up kernel holds them all in registers).
+constexpr int kGramSplitMaxParts = 8;
+
 constexpr size_t kAlign = 256;
 constexpr int kBarStride = 32;  // u32 between the grid-barrier counters (128 bytes)
 size_t align_up(size_t x);

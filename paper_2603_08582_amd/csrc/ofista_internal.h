@@ -264,6 +264,12 @@ __device__ inline double scalars_tree_sum(double v, double *red) {
 }
 __device__ inline void pulse_scalars(const ScalarArgs &a, double *red) {
   DevScalars *scal = a.scal;
+  // every value from memory is read before the reductions, so they arrive
+  // in one round trip rather than one after another
+  const double sigma2 = a.sig2[a.s];
+  const double rho_kept = scal->rho, acc_kept = scal->sig2_acc, L_prev = scal->L;
+  const double lam_kept = scal->lam;
+  const unsigned dbmax_bits = scal->dbmax_bits;
   double rho = 0.0;
   if (a.new_rho) {
     double pr = 0.0, pm = 0.0;
@@ -276,22 +282,23 @@ __device__ inline void pulse_scalars(const ScalarArgs &a, double *red) {
     rho = rs / ms;
   }
   if (threadIdx.x != 0) return;
-  if (a.first)
-    scal->lam = a.rel ? a.lam_in * static_cast<double>(__uint_as_float(scal->dbmax_bits)) : a.lam_in;
-  const double sigma2 = a.sig2[a.s];
+  const double lam =
+      a.first ? (a.rel ? a.lam_in * static_cast<double>(__uint_as_float(dbmax_bits)) : a.lam_in)
+              : lam_kept;
   double acc = sigma2;
   if (a.new_rho) {
     scal->rho = rho;
   } else {
-    rho = scal->rho;
-    acc += scal->sig2_acc;
+    rho = rho_kept;
+    acc += acc_kept;
   }
-  const double L = a.lip == 0 ? rho + acc : scal->L + sigma2;
+  const double L = a.lip == 0 ? rho + acc : L_prev + sigma2;
+  scal->lam = lam;
   scal->sig2_acc = acc;
   scal->sigma2 = sigma2;
   scal->L = L;
   scal->tau = 1.0 / L;
-  scal->alpha = scal->lam / L;
+  scal->alpha = lam / L;
 }
 
 hipError_t launch_scalars(const ScalarArgs &a, hipStream_t st);
