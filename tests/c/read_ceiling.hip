@@ -234,8 +234,8 @@ int main(int argc, char **argv) {
   std::vector<size_t> sizes;
   for (int a = 1; a < argc; ++a) {
     const double mb = std::atof(argv[a]);
-    if (!(mb > 0.0) || mb > 65536.0) {
-      std::fprintf(stderr, "usage: read_ceiling [MBYTES ...] (each in (0, 65536])\n");
+    if (!(mb >= 0.001) || mb > 65536.0) {
+      std::fprintf(stderr, "usage: read_ceiling [MBYTES ...] (each in [0.001, 65536])\n");
       return 2;
     }
     sizes.push_back(static_cast<size_t>(mb * 1e6) / 16 * 16);

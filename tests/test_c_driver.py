@@ -78,7 +78,7 @@ def test_read_ceiling_builds_and_rejects_bad_sizes():
     exe = ROOT / "tests" / "c" / "read_ceiling"
     if not exe.exists():
         pytest.skip("read_ceiling not built")
-    for bad in (["-5"], ["0"], ["x"], ["70000"], ["--tiles"], ["--tiles", "10"],
+    for bad in (["-5"], ["0"], ["0.0001"], ["x"], ["70000"], ["--tiles"], ["--tiles", "10"],
                 ["--tiles", "40000"]):
         r = subprocess.run([str(exe), *bad], capture_output=True, text=True)
         assert r.returncode == 2 and "usage" in r.stderr, bad
