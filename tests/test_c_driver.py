@@ -136,3 +136,5 @@ def test_driver_matches_binding_and_oracle(tmp_path, dictionary):
     ref = o.image()
     err = np.linalg.norm(img_c.astype(np.complex128) - ref) / np.linalg.norm(ref)
     assert err < 1e-4, err
+    emax = np.max(np.abs(img_c.astype(np.complex128) - ref)) / np.max(np.abs(ref))
+    assert emax < 1e-4, emax  # element by element against the largest magnitude
