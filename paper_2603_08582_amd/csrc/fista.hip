@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_step_update(StepArgs a) {
   }
 }
 
-template <int CH, bool CACHED>
+template <int CH, bool CACHED, bool NTSTORE>
 __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
   __shared__ float4 colbuf[CH][4][64];
 
@@ -322,10 +322,18 @@ __global__ __launch_bounds__(256) void k_step_tiles(StepArgs a) {
       }
       // column slots are written source-major (scattered target-major stores
       // into the saturated read stream took 3.5% longer at N = 16384)
-      a.Q[slot_index(I, J, a.nb) * kTile + lane] = s;
+      float4 *dst = a.Q + slot_index(I, J, a.nb) * kTile + lane;
+      if constexpr (NTSTORE)
+        __builtin_nontemporal_store(f32x4{s.x, s.y, s.z, s.w}, reinterpret_cast<f32x4 *>(dst));
+      else
+        *dst = s;
     }
   }
-  reinterpret_cast<float *>(a.Q + slot_index(J0, I, a.nb) * kTile + row0)[lane] = v[0];
+  float *rdst = reinterpret_cast<float *>(a.Q + slot_index(J0, I, a.nb) * kTile + row0) + lane;
+  if constexpr (NTSTORE)
+    __builtin_nontemporal_store(v[0], rdst);
+  else
+    *rdst = v[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -941,7 +949,8 @@ hipError_t launch_scale(const float2 *x, float scale, int n, float2 *out, hipStr
 
 hipError_t launch_step_tiles(const StepArgs &a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (a.chunk != 2) return hipErrorInvalidValue;
-  auto kern = a.h_cached ? k_step_tiles<2, true> : k_step_tiles<2, false>;
+  auto kern = a.h_cached ? (a.slot_nt ? k_step_tiles<2, true, true> : k_step_tiles<2, true, false>)
+                         : (a.slot_nt ? k_step_tiles<2, false, true> : k_step_tiles<2, false, false>);
   if (t0)
     hipExtLaunchKernelGGL(kern, dim3(a.nitems), dim3(256), 0, st, t0, t1, 0, a);
   else

@@ -97,6 +97,7 @@ struct Layout {
   int gparts = 0;
   int gram_kb = kGramKBSmall;  // frequencies per LDS stage of the FP32 Gram update
   bool h_cached = true;        // the tile pass reads H with cached loads
+  bool slot_nt = false;        // the tile pass writes its slots with nontemporal stores
   // byte offsets
   size_t H, A, b, c0, c1, z0, z1, w0, w1, Q, slot0, slot1, scal, pos,
       sig2, gtoep, tile_ij, tile_row0, items, echo_tmp, Ahi, Alo;

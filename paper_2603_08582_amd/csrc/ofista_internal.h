@@ -182,6 +182,7 @@ struct StepArgs {
   float2 *urec;  // if set, the update stores u = z - tau (H z - b) here
   int nb, N, nitems, chunk;
   int h_cached;  // tile pass: cached (H fits the last-level cache) or nontemporal H loads
+  int slot_nt;   // tile pass: nontemporal slot stores (the slots exceed the last-level cache)
   float beta;
   // store-all comparator: the update sums nchunks partial rows of P (stride
   // Npad) instead of the tile-pass slots

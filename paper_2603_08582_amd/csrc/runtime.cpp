@@ -627,6 +627,7 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.nitems = static_cast<int>(L.nitems);
     a.chunk = L.chunk;
     a.h_cached = L.h_cached;
+    a.slot_nt = L.slot_nt;
     a.beta = static_cast<float>(beta);
     if (L.store) {
       // gradient from the n stored pulses: two passes over the stacked rows
@@ -835,6 +836,7 @@ ofista_status reverse_pulse(ofista_ctx *c, int n, int j) {
     sa.nitems = static_cast<int>(L.nitems);
     sa.chunk = L.chunk;
     sa.h_cached = L.h_cached;
+    sa.slot_nt = L.slot_nt;
     OF_CK(c, launch_step_tiles(sa, c->st));
     a.ubar_cur = ubar[cur];
     a.cpart_cur = cpart[cur];
