@@ -178,7 +178,6 @@ struct StepArgs {
   double *slot_cur;
   const DevScalars *scal;
   const WorkItem *items;
-  const int *tile_row0;
   float2 *urec;  // if set, the update stores u = z - tau (H z - b) here
   int nb, N, nitems, chunk;
   int h_cached;  // tile pass: cached (H fits the last-level cache) or nontemporal H loads
@@ -200,7 +199,6 @@ constexpr int kResMaxParts = 1024; // update parts kUpdSplit * nb (summed per th
 struct ResidentArgs {
   const float2 *H;
   const WorkItem *items;
-  const int *tile_row0;
   const float2 *b;
   float2 *zbuf[2], *cbuf[2], *wbuf[2];
   double *slots[2];

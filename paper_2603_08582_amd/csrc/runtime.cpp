@@ -565,7 +565,6 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     ResidentArgs a{};
     a.H = d.H;
     a.items = d.items;
-    a.tile_row0 = d.tile_row0;
     a.b = d.b;
     for (int p = 0; p < 2; ++p) {
       a.zbuf[p] = d.zbuf[p];
@@ -618,7 +617,6 @@ ofista_status reconstruct_impl(ofista_ctx *c, int32_t iters, void *d_coef_out, i
     a.slot_cur = d.slots[p ^ 1];
     a.scal = d.scal;
     a.items = d.items;
-    a.tile_row0 = d.tile_row0;
     a.urec = seg_j >= 0 ? seg_ptr(c, L.seg_u, static_cast<size_t>(seg_j) * L.rec_iters + k,
                                   static_cast<size_t>(L.Npad) * sizeof(float2))
                         : nullptr;
@@ -830,7 +828,6 @@ ofista_status reverse_pulse(ofista_ctx *c, int n, int j) {
     sa.wc = ubar[cur];
     sa.Q = d.Q;
     sa.items = d.items;
-    sa.tile_row0 = d.tile_row0;
     sa.nb = L.nb;
     sa.N = L.N;
     sa.nitems = static_cast<int>(L.nitems);
