@@ -29,9 +29,9 @@
  *   to ofista_create and returns without waiting, unless stated otherwise.
  * - A ctx is single-threaded: calls on one ctx must not overlap.
  * - ofista_reset, ofista_push_pulse (without validate_input),
- *   ofista_reconstruct and ofista_reconstruct_static (launch-pair step kernel;
- *   either storage, any dictionary) enqueue kernels and device-to-device
- *   copies only: no host
+ *   ofista_reconstruct (launch-pair step kernel; either storage, any
+ *   dictionary) and ofista_reconstruct_static (GRAM storage) enqueue kernels
+ *   and device-to-device copies only: no host
  *   synchronisation and no memset, so a sequence of them can be captured from
  *   the ctx's stream into a HIP graph and replayed.  The host side of the ctx
  *   (pulse count, step parity, momentum t) advances when the calls are made,
