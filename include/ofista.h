@@ -28,7 +28,8 @@
  * - Every call that takes a ctx enqueues its device work on the stream given
  *   to ofista_create and returns without waiting, unless stated otherwise.
  * - A ctx is single-threaded: calls on one ctx must not overlap.
- * - ofista_reset, ofista_push_pulse (without validate_input),
+ * - ofista_reset, ofista_push_pulse (without validate_input and without
+ *   recording, whose checkpoints synchronise),
  *   ofista_reconstruct (launch-pair step kernel; either storage, any
  *   dictionary) and ofista_reconstruct_static (GRAM storage) enqueue kernels
  *   and device-to-device copies only: no host
