@@ -398,7 +398,7 @@ def main():
                                   if session_mode else f"P={P} pulses")
                                + f", m={m} FISTA steps per pulse, one step = one image",
                    "N": N, "M": M, "K": K, "pulses": pulses_per_step[0], "positions": P,
-                   "inner_steps": m, "seed": s.seed,
+                   "inner_steps": m, "seed": s.seed, "generator": "numpy PCG64",
                    "storage": "packed Hermitian upper tiles 64x64, complex64",
                    "step_kernel": args.step_kernel,
                    "launch": "HIP graph replay of the captured step" if graph_mode
